@@ -1,0 +1,231 @@
+/*
+ * bem.h -- C ABI of the MI355X (gfx950) boundary element library for normal
+ * non-adhesive and adhesive contact of power-law graded elastic half-spaces,
+ * after Li & Popov, "Boundary element method for normal non-adhesive and
+ * adhesive contacts of power-law graded elastic materials" (arXiv:1612.08395).
+ *
+ * Material (Section 2.1, Eq. 1): E(z) = E0 (z / c0)^k with -1 < k < 1 and a
+ * constant Poisson ratio nu.  Surface: nx x ny rectangular elements of size
+ * dx x dy carrying constant pressure, collocation at element centres.
+ *
+ * Conventions shared by every entry point
+ *  - Arrays are row-major ny x nx (row index y, x contiguous), FP64 unless
+ *    stated.  Host arrays are owned by the caller; they are read or written
+ *    only during the call and never retained.
+ *  - Device-pointer variants (suffix _dev) take pointers into the memory of
+ *    the current HIP device; their element type is given per argument.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Host-array entry
+ *    points return after the stream has finished their work; _dev entry
+ *    points return once the work is queued.
+ *  - Signs: pressure p > 0 is compressive; displacement u > 0 points into
+ *    the half-space; h is the gap between the undeformed surfaces; the gap
+ *    after deformation is g = u + h - d (contact: g = 0, separation: g > 0).
+ *  - Every function returns an int status: 0 success, > 0 a warning (the
+ *    outputs are valid), < 0 an error (outputs untouched unless stated).
+ *    bem_last_error() returns a message for the calling thread.
+ *  - Handles are library-owned, hold device memory of the device that was
+ *    current when they were created, and are released with the matching
+ *    _free call.  One handle may be used from several threads only if the
+ *    calls do not overlap.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BEM_OK = 0,
+  BEM_ENOCONV = 1,       /* warning: iteration limit reached; outputs hold the last iterate */
+  BEM_EFLOOR = 2,        /* warning: MIXED solve stopped at its FP32 rounding floor */
+  BEM_EINVAL = -1,       /* invalid argument (range, size, non-finite input) */
+  BEM_ENOMEM = -2,       /* device memory allocation failed */
+  BEM_EDEVICE = -3,      /* HIP runtime error */
+  BEM_EUNSUPPORTED = -4, /* valid request outside what this library implements */
+  BEM_ENUMERIC = -5      /* non-finite value appeared during a solve */
+};
+
+/* Arithmetic of the convolution and vector updates.  Influence coefficients,
+ * kernel spectrum generation, dot products / step lengths and force / area
+ * sums are FP64 in both. */
+enum { BEM_FP64 = 0, BEM_MIXED = 1 };
+
+typedef struct bem_influence_s* bem_influence_t;
+
+/* Largest supported grid side (padded transform 8192). */
+#define BEM_MAX_N 4096
+
+/*
+ * bem_influence_ex -- build the influence operator of Section 2.1.
+ *
+ * Computes, in FP64 on the device, the influence coefficients of Eqs. 8-10,
+ *   K(di, dj) = integral over [(di-1/2)dx, (di+1/2)dx] x [(dj-1/2)dy, (dj+1/2)dy]
+ *               of (a^2 + b^2)^(-(1+k)/2) da db,
+ * for 0 <= di < nx, 0 <= dj < ny, and the spectrum of K laid out on the
+ * zero-padded My x Mx grid (Eq. 13; Mx, My = the smallest powers of two
+ * >= max(2n, 64)), kept in FP64 and FP32 and pre-multiplied by
+ *   C = alpha(k, nu) (1 - nu^2) c0^k / E0      (Eqs. 2-4, 12).
+ * The paper computes this matrix once per calculation; reuse the handle.
+ *
+ * Errors: BEM_EINVAL if nx, ny < 1, dx, dy, E0, c0 <= 0 or non-finite,
+ * k outside (-1, 1), nu outside [0, 0.5); BEM_EUNSUPPORTED if nx or ny
+ * exceeds BEM_MAX_N; BEM_ENOMEM, BEM_EDEVICE.  *out is set only on success.
+ */
+int bem_influence_ex(int nx, int ny, double dx, double dy, double k, double nu, double E0,
+                     double c0, bem_influence_t* out);
+
+/* bem_influence -- square elements (dy = dx) and E0 = c0 = 1. */
+int bem_influence(int nx, int ny, double dx, double k, double nu, bem_influence_t* out);
+
+int bem_influence_free(bem_influence_t K);
+
+/* Scalars of a handle: the prefactor C of Eq. 12, alpha of Eq. 3, K(0, 0),
+ * the padded transform sizes and the device bytes the handle holds. */
+typedef struct {
+  int nx, ny, Mx, My;
+  double dx, dy, k, nu, E0, c0;
+  double alpha, C, K00;
+  long long device_bytes;
+} bem_influence_info_t;
+int bem_influence_info(bem_influence_t K, bem_influence_info_t* info);
+
+/*
+ * bem_influence_coeffs -- copy the influence coefficients to the host.
+ * K_out: (2ny - 1) x (2nx - 1) FP64, row-major, offset (di, dj) at row
+ * dj + ny - 1, column di + nx - 1 (K is even in both offsets, Eq. 10).
+ */
+int bem_influence_coeffs(bem_influence_t K, double* K_out);
+
+/*
+ * bem_convolve -- surface displacement from pressure, Eqs. 7 / 12 / 13:
+ *   u(i, j) = C * sum_{i', j'} K(i - i', j - j') p(i', j'),
+ * the non-periodic half-space sum, evaluated as a zero-padded FFT product
+ * in FP64.  p, u: host, ny x nx FP64 (may not alias).
+ */
+int bem_convolve(bem_influence_t K, const double* p, double* u, void* stream);
+
+/*
+ * bem_convolve_dev -- the same on device arrays, in the given precision:
+ * precision BEM_FP64: p, u are double*; BEM_MIXED: float* (FP32 transforms).
+ * p and u are ny x nx device arrays and may alias.  Uses a scratch buffer
+ * owned by the handle: calls on one handle must not run concurrently on
+ * different streams.
+ */
+int bem_convolve_dev(bem_influence_t K, int precision, const void* p, void* u, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Contact solves
+ * ------------------------------------------------------------------------- */
+
+typedef struct bem_state_s* bem_state_t;
+
+enum { BEM_CTRL_INDENT = 0, BEM_CTRL_FORCE = 1 };
+
+typedef struct {
+  int control;       /* BEM_CTRL_INDENT: indentation d given (BEM_CTRL_FORCE: not
+                        implemented, returns BEM_EUNSUPPORTED) */
+  int precision;     /* BEM_FP64 or BEM_MIXED */
+  double d;          /* indentation: rigid-body approach of the indenter */
+  double F;          /* target normal force (BEM_CTRL_FORCE) */
+  double gamma;      /* work of adhesion gamma12 (Eq. 20); 0 = non-adhesive */
+  double p_crit;     /* > 0: detachment stress used as given; <= 0: from gamma
+                        by Eq. 24 with the corrected c1(k) of Table 1 */
+  double d_preload;  /* adhesive solve without a contact set in the state:
+                        the set is first made by a non-adhesive solve at
+                        max(d, d_preload) (Section 3.1) */
+  double tol;        /* relative tolerance; <= 0: 1e-12 (FP64), 1e-6 (MIXED) */
+  int max_iter;      /* CG iteration limit per solve; <= 0: 20000 */
+  int stall_limit;   /* stop after this many iterations without a new smallest
+                        residual (MIXED rounding floor); < 0: never;
+                        0: default (50 for MIXED, never for FP64) */
+} bem_params;
+
+/* Fills *prm with the defaults (indentation control, FP64, d = 0, no
+ * adhesion). */
+void bem_params_init(bem_params* prm);
+
+typedef struct {
+  double F;                  /* normal force dx dy sum p (FP64 sum) */
+  double area;               /* contact area: contact elements * dx dy */
+  double d;                  /* indentation of this solve */
+  double residual;           /* final sqrt(sum_Ic g^2) / sqrt(sum_Ic (d-h)^2) */
+  double p_crit;             /* detachment stress used (adhesive), else 0 */
+  long long n_contact;       /* elements in contact */
+  long long n_penetrating;   /* adhesive: elements off the contact set with g < 0 */
+  int iters;                 /* CG iterations of this solve (all detach rounds) */
+  int detach_rounds;         /* adhesive: rounds that removed elements */
+  int status;                /* BEM_OK, BEM_ENOCONV, BEM_EFLOOR or BEM_ENUMERIC */
+} bem_result;
+
+/* Solver state: pressure, contact set and work buffers, device-resident.
+ * A state carries the previous solve's pressure and contact set into the
+ * next solve (warm start); a fresh state has neither. */
+int bem_state_create(bem_influence_t K, bem_state_t* out);
+int bem_state_free(bem_state_t st);
+/* Import / export the warm-start data as host arrays (checkpoint / resume).
+ * p: ny x nx FP64 (NULL on set = zeros); contact: ny x nx bytes, non-zero =
+ * in contact (NULL on set: p > 0). */
+int bem_state_set(bem_state_t st, const double* p, const unsigned char* contact);
+int bem_state_get(bem_state_t st, double* p, unsigned char* contact);
+
+/*
+ * bem_solve -- one contact solve at indentation prm->d for the gap profile h
+ * (host, ny x nx FP64, the gap between the undeformed surfaces).
+ *
+ * Non-adhesive (gamma = 0 and p_crit <= 0): pressure p >= 0 with g = 0 where
+ * p > 0 and g >= 0 elsewhere, by the constrained conjugate-gradient method
+ * the paper uses for its inverse problem (Section 2.1), displacement
+ * controlled.  The solution is unique; a warm start changes only the
+ * iteration count.
+ *
+ * Adhesive (gamma > 0 or p_crit > 0), one pull-off step of Section 3.1: with
+ * the state's contact set A held fixed, u = d - h on A and p = 0 off A; then
+ * every element of A with -p > p_crit detaches, all at once, and the solve is
+ * repeated until no element violates the criterion (Eq. 24).  Adhesion
+ * requires dx = dy (Eqs. 21-24 are for square elements), else
+ * BEM_EUNSUPPORTED.
+ *
+ * state: NULL = a temporary state (cold start); otherwise used and updated.
+ * p_out (FP64), contact_out (bytes, 1 = contact), u_out (FP64 surface
+ * displacement): host ny x nx arrays or NULL.  res: may be NULL.
+ * Returns BEM_OK, BEM_ENOCONV / BEM_EFLOOR (warnings; outputs hold the last
+ * iterate), BEM_ENUMERIC, BEM_EINVAL (non-finite h or d, bad parameters),
+ * BEM_EUNSUPPORTED (force control; adhesion with dx != dy).
+ */
+int bem_solve(bem_influence_t K, const double* h, const bem_params* prm, bem_state_t state,
+              double* p_out, unsigned char* contact_out, double* u_out, bem_result* res,
+              void* stream);
+
+/* bem_solve_dev -- as bem_solve with device arrays: h, p_out, u_out are
+ * double*, contact_out unsigned char* (each output may be NULL).  h is read
+ * in place (not copied); non-finite values in it surface as BEM_ENUMERIC. */
+int bem_solve_dev(bem_influence_t K, const double* h, const bem_params* prm, bem_state_t state,
+                  double* p_out, unsigned char* contact_out, double* u_out, bem_result* res,
+                  void* stream);
+
+/*
+ * bem_sweep -- a sequence of solves at the indentations d_list[0..n_steps),
+ * warm-started from step to step on the device (Section 3.1).  With
+ * adhesion, a step whose d is below the previous step's is a pull-off step
+ * (adhesive solve); every other step is a non-adhesive (loading) solve.
+ * h: host ny x nx FP64.  res: n_steps results.  state: NULL = temporary.
+ */
+int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const double* d_list,
+              int n_steps, bem_state_t state, bem_result* res, void* stream);
+
+/* Corrected c1(k) of Table 1: the tabulated value at k = -0.9, ..., 0.9 and a
+ * natural cubic spline of ln c1 over k in between (NaN outside (-1, 1)). */
+double bem_c1(double k);
+
+/* Detachment stress of Eq. 24 for square elements of side dx, with c1 from
+ * bem_c1 (NaN on invalid arguments). */
+double bem_p_crit(double k, double nu, double gamma, double dx, double E0, double c0);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

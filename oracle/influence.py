@@ -130,6 +130,24 @@ def influence_quarter(nx, ny, dx, dy, k):
     return Kq
 
 
+def influence_at(di, dj, dx, dy, k):
+    """K at arbitrary offsets (arrays di, dj), with the same rules as
+    ``influence_quarter`` (for sampled checks on grids too large to tabulate)."""
+    check_k(k)
+    di = np.abs(np.asarray(di, dtype=np.int64)).ravel()
+    dj = np.abs(np.asarray(dj, dtype=np.int64)).ravel()
+    out = np.empty(di.shape)
+    ring = np.maximum(di, dj)
+    for order, sel in ((20, (ring > NEAR) & (ring <= MID)), (10, ring > MID)):
+        for j in np.unique(dj[sel]):
+            rows = sel & (dj == j)
+            out[rows] = _gauss_row(int(j), dx, dy, k, order, di[rows].astype(np.float64))
+    for idx in np.nonzero(ring <= NEAR)[0]:
+        a, b = int(di[idx]), int(dj[idx])
+        out[idx] = element_integral((a - 0.5) * dx, (a + 0.5) * dx, (b - 0.5) * dy, (b + 0.5) * dy, k)
+    return out
+
+
 def influence_full(Kq):
     """The (2ny-1) x (2nx-1) array of K over all offsets, centred at
     (ny-1, nx-1): K is even in each offset (Eq. 10)."""

@@ -1,0 +1,151 @@
+// Launchers of the conjugate-gradient kernels, instantiated per precision in
+// cg_f32.hip and cg_f64.hip.
+#pragma once
+#include "cg_kernels.h"
+#include "launch.h"
+
+namespace bem {
+
+template <typename T>
+struct CgBufs {
+  T* p;
+  T* t;
+  T* g;
+  T* hd;
+  uint8_t* mask;
+  cplx<T>* S;
+  double* part;
+  CgScal* sc;
+};
+
+inline int ew_blocks(size_t n) {
+  size_t b = (n + EW_THREADS - 1) / EW_THREADS;
+  if (b < 1) b = 1;
+  return (int)(b > EW_MAX_BLOCKS ? EW_MAX_BLOCKS : b);
+}
+
+template <typename T, bool FS>
+hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
+                               hipStream_t s) {
+  const int nrp = (g.ny + 1) / 2;
+  hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    UpdatePro<T, FS> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, FS>>), dim3(nrp), dim3(NT), 0, s, up, b.S,
+                       g.nx, g.ny, K.twx);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
+  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    GapEpi<T, FS> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, FS>>), dim3(nrp), dim3(NT), 0, s, b.S, g.nx,
+                       g.ny, K.twx, ge);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    DirPro<T, FS> dp{b.t, b.g, b.p, b.mask, b.sc, g.nx};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, FS>>), dim3(nrp), dim3(NT), 0, s, dp, b.S,
+                       g.nx, g.ny, K.twx);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
+  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    DotsEpi<T> de{b.g, b.t, b.sc, b.part, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T>>), dim3(nrp), dim3(NT), 0, s, b.S, g.nx,
+                       g.ny, K.twx, de);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
+                                bool fixed_set, int n, hipStream_t s) {
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, s)
+                             : launch_cg_iteration<T, false>(g, K, b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_make_hd(const double* h, double d, T* hd, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_make_hd<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, h, d, hd, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cold_start(T* p, const T* hd, double inv_ck00, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cold_start<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, p, hd, inv_ck00,
+                     n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prepare(T* t, T* p, const uint8_t* mask, bool clip, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, t, p, mask,
+                     clip ? 1 : 0, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finalize(const CgBufs<T>& b, bool fixed_set, size_t n, hipStream_t s) {
+  if (fixed_set)
+    hipLaunchKernelGGL((k_finalize<T, true>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p, b.g,
+                       b.mask, b.sc, b.part, n);
+  else
+    hipLaunchKernelGGL((k_finalize<T, false>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p, b.g,
+                       b.mask, b.sc, b.part, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_detach(const CgBufs<T>& b, double pcrit, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_detach<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p, b.mask, pcrit,
+                     b.sc, b.part, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_to_f64(const T* src, double* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f64<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_from_f64(const double* src, T* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_f64<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, size_t n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_u_from_gap<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, g, h, d, u, n);
+  return hipGetLastError();
+}
+
+#define BEM_INSTANTIATE_CG(T)                                                                    \
+  template hipError_t launch_cg_iterations<T>(const Geom&, const SpecView<T>&, const CgBufs<T>&, \
+                                              bool, int, hipStream_t);                           \
+  template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \
+  template hipError_t launch_cold_start<T>(T*, const T*, double, size_t, hipStream_t);           \
+  template hipError_t launch_prepare<T>(T*, T*, const uint8_t*, bool, size_t, hipStream_t);      \
+  template hipError_t launch_finalize<T>(const CgBufs<T>&, bool, size_t, hipStream_t);          \
+  template hipError_t launch_detach<T>(const CgBufs<T>&, double, size_t, hipStream_t);          \
+  template hipError_t launch_to_f64<T>(const T*, double*, size_t, hipStream_t);                  \
+  template hipError_t launch_from_f64<T>(const double*, T*, size_t, hipStream_t);                \
+  template hipError_t launch_u_from_gap<T>(const T*, const double*, double, double*, size_t,     \
+                                           hipStream_t);
+
+}  // namespace bem

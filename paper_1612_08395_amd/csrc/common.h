@@ -1,0 +1,58 @@
+// Shared device-side helpers of the BEM library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bem {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+
+// LDS index padding: one spare slot every 32 elements breaks the power-of-two
+// strides of the Stockham write pattern across the LDS banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 5) + 1; }
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+// Block-wide FP64 sum; every thread passes its value, the result is valid in
+// every thread.  Fixed combination order (wave shuffles, then waves in index
+// order), so the result is bitwise reproducible.  `red` holds >= 16 doubles.
+template <int NTHR>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  static_assert(NTHR % 64 == 0 && NTHR <= 1024, "block size");
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  constexpr int NW = NTHR / 64;
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+}  // namespace bem

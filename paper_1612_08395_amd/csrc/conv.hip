@@ -1,0 +1,60 @@
+// Plain convolution u = C K * p (Eq. 13 with zero padding), FP32 and FP64.
+#include "conv_kernels.h"
+#include "launch.h"
+
+namespace bem {
+
+template <typename T>
+hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int* done,
+                      hipStream_t s) {
+  const int W = col_width<T>(g.Ly, g.Lx);
+  return dispatch_L(g.Ly, [&](auto LYc) -> hipError_t {
+    constexpr int LY = decltype(LYc)::value;
+    return dispatch_W(W, [&](auto Wc) -> hipError_t {
+      constexpr int WW = decltype(Wc)::value;
+      if constexpr (WW > col_width_lds<T>(LY)) {
+        return hipErrorInvalidValue;
+      } else {
+        constexpr int NT = col_threads(WW, LY);
+        hipLaunchKernelGGL((k_col_conv<T, LY, WW, NT>), dim3(g.Lx / WW), dim3(NT), 0, s, S, g.Lx,
+                           g.ny, K.KT, g.kpitch, K.twy, done);
+        return hipGetLastError();
+      }
+    });
+  });
+}
+
+template <typename T>
+hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cplx<T>* S,
+                       hipStream_t s) {
+  hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    PlainLoad<T> pro{p, g.nx};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
+                       pro, S, g.nx, g.ny, K.twx);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  e = launch_col<T>(g, K, S, nullptr, s);
+  if (e != hipSuccess) return e;
+  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    PlainStore<T> epi{u, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
+                       S, g.nx, g.ny, K.twx, epi);
+    return hipGetLastError();
+  });
+}
+
+template hipError_t launch_col<float>(const Geom&, const SpecView<float>&, cplx<float>*, const int*,
+                                      hipStream_t);
+template hipError_t launch_col<double>(const Geom&, const SpecView<double>&, cplx<double>*,
+                                       const int*, hipStream_t);
+template hipError_t launch_conv<float>(const Geom&, const SpecView<float>&, const float*, float*,
+                                       cplx<float>*, hipStream_t);
+template hipError_t launch_conv<double>(const Geom&, const SpecView<double>&, const double*,
+                                        double*, cplx<double>*, hipStream_t);
+
+}  // namespace bem

@@ -1,0 +1,259 @@
+// Zero-padded 2-D FFT convolution u = C K * p of Eq. 13, as three sweeps.
+//
+// Layout.  The field is ny x nx (row index y, x contiguous).  The padded
+// transform is My x Mx (powers of two, My >= 2ny, Mx >= 2nx), half lengths
+// Ly = My/2 and Lx = Mx/2.  Only the first ny rows and nx columns of the
+// padded input are non-zero and only those outputs are kept, which the
+// sweeps exploit:
+//
+//  * row sweep (R2C): two real rows a, b are packed as one complex row
+//    z = a + i b.  Because z is zero on [Mx/2, Mx), its Mx-point DFT splits
+//    into two Lx-point DFTs (even bins: DFT(z); odd bins: DFT(z w^n),
+//    w = exp(-2 pi i / Mx)).  The real-row spectra A, B (bins 0..Lx) are
+//    untangled from Z[k] and conj(Z[Mx - k]).  Bins 0 and Lx of a real row
+//    are real, so slot 0 stores (A[0], A[Lx]): the spectrum S has exactly
+//    Lx complex columns and row pitch Lx.
+//  * column sweep: for each spectrum column, the My-point DFT of the ny
+//    non-zero values (same even/odd split), multiplication by the real,
+//    even kernel spectrum, inverse DFT, and only outputs y < ny kept
+//    (again two Ly-point transforms).  Column 0 carries the real DC and
+//    Nyquist columns packed as re/im; it is multiplied by
+//    ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]).
+//  * row sweep (C2R): Hermitian completion of the two rows' spectra,
+//    Lx-point inverse DFTs of the even and odd bins, outputs x < nx kept.
+//
+// The kernel spectrum is stored transposed, KT[kx * kpitch + ky] for
+// kx in [0, Lx], ky in [0, Ly] (the other half of ky by evenness), and is
+// pre-multiplied by C / (Mx My), so no other scaling is applied.
+//
+// Prologue / epilogue functors fuse the conjugate-gradient vector work into
+// the row sweeps: a prologue supplies the value at (y, x) (and may update
+// state there), an epilogue consumes u at (y, x).  Both may accumulate FP64
+// partial sums; finish() reduces them per workgroup.
+#pragma once
+#include "common.h"
+#include "fft_lds.h"
+
+namespace bem {
+
+template <typename T>
+struct PlainLoad {
+  const T* in;
+  int nx;
+  __device__ bool skip() const { return false; }
+  __device__ void begin() {}
+  __device__ T load(int y, int x) { return in[(size_t)y * nx + x]; }
+  template <int NTHR>
+  __device__ void finish(double*) {}
+};
+
+template <typename T>
+struct PlainStore {
+  T* out;
+  int nx;
+  __device__ bool skip() const { return false; }
+  __device__ void begin() {}
+  __device__ void store(int y, int x, T v) { out[(size_t)y * nx + x] = v; }
+  template <int NTHR>
+  __device__ void finish(double*) {}
+};
+
+template <typename T, int L, int NTHR, class Pro>
+__global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
+                                                  int ny, const cplx<T>* __restrict__ tw) {
+  constexpr int STR = lds_len(L);
+  __shared__ cplx<T> lds[2 * STR];
+  __shared__ double red[64];
+  Pro pro = pro_arg;
+  if (pro.skip()) return;
+  pro.begin();
+  const int ya = 2 * blockIdx.x, yb = ya + 1;
+  const bool hasb = yb < ny;
+  for (int n = threadIdx.x; n < L; n += NTHR) {
+    cplx<T> z = {T(0), T(0)};
+    if (n < nx) {
+      z.x = pro.load(ya, n);
+      if (hasb) z.y = pro.load(yb, n);
+    }
+    lds[lds_pad(n)] = z;
+    lds[STR + lds_pad(n)] = cmul(z, tw[n]);
+  }
+  __syncthreads();
+  fft_lds<T, L, -1, 2, NTHR, STR>(lds, tw);
+  const cplx<T>* E = lds;
+  const cplx<T>* O = lds + STR;
+  cplx<T>* Sa = S + (size_t)ya * L;
+  cplx<T>* Sb = S + (size_t)yb * L;
+  const T half = T(0.5);
+  for (int k = threadIdx.x; k < L; k += NTHR) {
+    if (k == 0) {
+      const cplx<T> z0 = E[lds_pad(0)], zl = E[lds_pad(L / 2)];
+      Sa[0] = {z0.x, zl.x};
+      if (hasb) Sb[0] = {z0.y, zl.y};
+    } else {
+      const int kp = k >> 1;
+      cplx<T> Z, Zp;
+      if ((k & 1) == 0) {
+        Z = E[lds_pad(kp)];
+        Zp = E[lds_pad(L - kp)];
+      } else {
+        Z = O[lds_pad(kp)];
+        Zp = O[lds_pad(L - 1 - kp)];
+      }
+      Sa[k] = {half * (Z.x + Zp.x), half * (Z.y - Zp.y)};
+      if (hasb) Sb[k] = {half * (Z.y + Zp.y), half * (Zp.x - Z.x)};
+    }
+  }
+  pro.template finish<NTHR>(red);
+}
+
+// Multiply the transformed columns held in LDS by the kernel spectrum.
+template <typename T, int LY, int W, int NTHR, int STR>
+__device__ __forceinline__ void col_multiply(cplx<T>* lds, int c0, int lx, const T* __restrict__ KT,
+                                             int kpitch) {
+  for (int f = threadIdx.x; f < 2 * W * LY; f += NTHR) {
+    const int s = f / LY, kp = f % LY;
+    const int c = s >> 1;
+    if (c0 + c == 0) continue;
+    const int ky = 2 * kp + (s & 1);
+    const int kq = ky <= LY ? ky : 2 * LY - ky;
+    const T kv = KT[(size_t)(c0 + c) * kpitch + kq];
+    cplx<T>* a = lds + s * STR + lds_pad(kp);
+    *a = cscale(*a, kv);
+  }
+  if (c0 == 0) {
+    // packed DC (re) / Nyquist (im) column: sequences 0 (even bins), 1 (odd)
+    const T* K0 = KT;
+    const T* K1 = KT + (size_t)lx * kpitch;
+    const T half = T(0.5);
+    for (int f = threadIdx.x; f <= LY; f += NTHR) {
+      // f in [0, LY/2]: even pair (f, LY - f); f in (LY/2, LY]: odd pair
+      int seq, i0, i1, ky;
+      if (f <= LY / 2) {
+        seq = 0;
+        i0 = f;
+        i1 = (LY - f) & (LY - 1);
+        ky = 2 * f;
+      } else {
+        seq = 1;
+        i0 = f - LY / 2 - 1;
+        i1 = LY - 1 - i0;
+        ky = 2 * i0 + 1;
+      }
+      if (seq == 1 && i0 >= LY / 2) continue;
+      const int kq = ky <= LY ? ky : 2 * LY - ky;
+      const T a = half * (K0[kq] + K1[kq]), b = half * (K0[kq] - K1[kq]);
+      cplx<T>* p0 = lds + seq * STR + lds_pad(i0);
+      cplx<T>* p1 = lds + seq * STR + lds_pad(i1);
+      const cplx<T> z0 = *p0, z1 = *p1;
+      *p0 = {a * z0.x + b * z1.x, a * z0.y - b * z1.y};
+      if (i1 != i0) *p1 = {a * z1.x + b * z0.x, a * z1.y - b * z0.y};
+    }
+  }
+}
+
+template <typename T, int LY, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int lx, int ny,
+                                                   const T* __restrict__ KT, int kpitch,
+                                                   const cplx<T>* __restrict__ tw,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int STR = lds_len(LY);
+  __shared__ cplx<T> lds[2 * W * STR];
+  const int c0 = blockIdx.x * W;
+  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
+    const int c = f % W, n = f / W;
+    cplx<T> x = {T(0), T(0)};
+    if (n < ny) x = S[(size_t)n * lx + c0 + c];
+    lds[(2 * c) * STR + lds_pad(n)] = x;
+    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  }
+  __syncthreads();
+  fft_lds<T, LY, -1, 2 * W, NTHR, STR>(lds, tw);
+  col_multiply<T, LY, W, NTHR, STR>(lds, c0, lx, KT, kpitch);
+  __syncthreads();
+  fft_lds<T, LY, +1, 2 * W, NTHR, STR>(lds, tw);
+  for (int f = threadIdx.x; f < W * ny; f += NTHR) {
+    const int c = f % W, n = f / W;
+    const cplx<T> e = lds[(2 * c) * STR + lds_pad(n)];
+    const cplx<T> o = lds[(2 * c + 1) * STR + lds_pad(n)];
+    S[(size_t)n * lx + c0 + c] = cadd(e, cmulc(o, tw[n]));
+  }
+}
+
+template <typename T, int L, int NTHR, class Epi>
+__global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
+                                                  const cplx<T>* __restrict__ tw, Epi epi_arg) {
+  constexpr int STR = lds_len(L);
+  __shared__ cplx<T> lds[2 * STR];
+  __shared__ double red[64];
+  Epi epi = epi_arg;
+  if (epi.skip()) return;
+  epi.begin();
+  const int ya = 2 * blockIdx.x, yb = ya + 1;
+  const bool hasb = yb < ny;
+  const cplx<T>* Sa = S + (size_t)ya * L;
+  const cplx<T>* Sb = S + (size_t)yb * L;
+  for (int k = threadIdx.x; k < L; k += NTHR) {
+    const cplx<T> A = Sa[k];
+    const cplx<T> B = hasb ? Sb[k] : cplx<T>{T(0), T(0)};
+    if (k == 0) {
+      lds[lds_pad(0)] = {A.x, B.x};        // Z[0]  = A[0]  + i B[0]
+      lds[lds_pad(L / 2)] = {A.y, B.y};    // Z[Lx] = A[Lx] + i B[Lx]
+    } else {
+      const cplx<T> Z = {A.x - B.y, A.y + B.x};    // A + i B
+      const cplx<T> Zm = {A.x + B.y, B.x - A.y};   // conj(A) + i conj(B) = Z[Mx - k]
+      const int km = 2 * L - k;
+      lds[(k & 1) * STR + lds_pad(k >> 1)] = Z;
+      lds[(km & 1) * STR + lds_pad(km >> 1)] = Zm;
+    }
+  }
+  __syncthreads();
+  fft_lds<T, L, +1, 2, NTHR, STR>(lds, tw);
+  for (int n = threadIdx.x; n < nx; n += NTHR) {
+    const cplx<T> z = cadd(lds[lds_pad(n)], cmulc(lds[STR + lds_pad(n)], tw[n]));
+    epi.store(ya, n, z.x);
+    if (hasb) epi.store(yb, n, z.y);
+  }
+  epi.template finish<NTHR>(red);
+}
+
+// Forward column transform of the (FP64) row spectrum of Q, and the real,
+// even kernel spectrum Khat(ky, kx) = 2 Re[Qhat(ky, kx) + Qhat(-ky, kx)]
+// written scaled, in FP64 and rounded to FP32.
+template <int LY, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_col_spectrum(const cplx<double>* __restrict__ S, int lx,
+                                                       int ny, const cplx<double>* __restrict__ tw,
+                                                       double* __restrict__ KT64,
+                                                       float* __restrict__ KT32, int kpitch,
+                                                       double scale) {
+  constexpr int STR = lds_len(LY);
+  __shared__ cplx<double> lds[2 * W * STR];
+  const int c0 = blockIdx.x * W;
+  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
+    const int c = f % W, n = f / W;
+    cplx<double> x = {0.0, 0.0};
+    if (n < ny) x = S[(size_t)n * lx + c0 + c];
+    lds[(2 * c) * STR + lds_pad(n)] = x;
+    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  }
+  __syncthreads();
+  fft_lds<double, LY, -1, 2 * W, NTHR, STR>(lds, tw);
+  for (int f = threadIdx.x; f < W * (LY + 1); f += NTHR) {
+    const int c = f / (LY + 1), ky = f % (LY + 1);
+    const int kn = (2 * LY - ky) & (2 * LY - 1);
+    const cplx<double> yk = lds[(2 * c + (ky & 1)) * STR + lds_pad(ky >> 1)];
+    const cplx<double> yn = lds[(2 * c + (kn & 1)) * STR + lds_pad(kn >> 1)];
+    const int cg = c0 + c;
+    const double v = 2.0 * (yk.x + yn.x) * scale;
+    KT64[(size_t)cg * kpitch + ky] = v;
+    KT32[(size_t)cg * kpitch + ky] = (float)v;
+    if (cg == 0) {
+      const double w = 2.0 * (yk.y + yn.y) * scale;
+      KT64[(size_t)lx * kpitch + ky] = w;
+      KT32[(size_t)lx * kpitch + ky] = (float)w;
+    }
+  }
+}
+
+}  // namespace bem

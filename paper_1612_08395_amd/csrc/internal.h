@@ -1,0 +1,48 @@
+// Internal declarations of the C ABI layer (not part of the public header).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+struct bem_influence_s {
+  int nx, ny;
+  double dx, dy, k, nu, E0, c0;
+  double alpha, C, K00;
+  int device;
+  bem::Geom g;
+  long long device_bytes = 0;
+  // FP64 influence coefficients, quarter 0 <= di < nx, 0 <= dj < ny
+  double* Kq = nullptr;
+  // kernel spectrum (Lx + 1) x kpitch, pre-scaled by C / (Mx My)
+  double* KT64 = nullptr;
+  float* KT32 = nullptr;
+  // twiddles exp(-2 pi i m / M)
+  bem::cplx<double>* twx64 = nullptr;
+  bem::cplx<double>* twy64 = nullptr;
+  bem::cplx<float>* twx32 = nullptr;
+  bem::cplx<float>* twy32 = nullptr;
+  // lazily allocated scratch of the convolution entry points
+  bem::cplx<double>* S64 = nullptr;
+  bem::cplx<float>* S32 = nullptr;
+  double* io64 = nullptr;
+};
+
+namespace bem {
+
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+int hip_fail(hipError_t e, const char* what);
+double alpha_kn(double k, double nu);
+bool is_finite(double v);
+
+int influence_build(bem_influence_s* h);
+void influence_release(bem_influence_s* h);
+int ensure_io(bem_influence_s* h);
+int convolve_device(bem_influence_s* h, int precision, const void* p, void* u, hipStream_t s);
+
+int dev_alloc(bem_influence_s* h, void** p, size_t bytes, const char* what);
+
+template <typename T>
+SpecView<T> spec_view(const bem_influence_s* h);
+
+}  // namespace bem

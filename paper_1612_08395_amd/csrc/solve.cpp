@@ -1,0 +1,556 @@
+// Contact solves: solver state, the host side of the device CG loop, the
+// adhesive detach / re-solve loop (Section 3.1), sweeps, Eq. 24.
+//
+// The host never takes part in an iteration: it queues a chunk of CG
+// iterations (six kernels each), copies the 200-byte scalar block back and
+// looks at the device-side `done` flag.  Kernels queued after convergence
+// return at once, so results do not depend on the chunking.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/bem.h"
+#include "cg_launch.h"
+#include "internal.h"
+
+using namespace bem;
+
+struct bem_state_s {
+  bem_influence_s* K = nullptr;
+  size_t n = 0;
+  int precision = -1;  // precision of the T buffers below (-1: none yet)
+  void* p = nullptr;
+  void* t = nullptr;
+  void* g = nullptr;
+  void* hd = nullptr;
+  void* S = nullptr;
+  uint8_t* mask = nullptr;
+  double* h64 = nullptr;
+  double* out64 = nullptr;
+  double* part = nullptr;
+  CgScal* sc = nullptr;
+  CgScal* sc_host = nullptr;  // pinned
+  bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
+  long long device_bytes = 0;
+};
+
+namespace {
+
+constexpr int kPartials = 8192;
+
+int salloc(bem_state_s* st, void** p, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, what);
+  }
+  st->device_bytes += (long long)bytes;
+  return BEM_OK;
+}
+
+void free_typed(bem_state_s* st) {
+  for (void** q : {&st->p, &st->t, &st->g, &st->hd, &st->S}) {
+    if (*q) hipFree(*q);
+    *q = nullptr;
+  }
+  st->precision = -1;
+}
+
+size_t tsize(int precision) { return precision == BEM_FP64 ? sizeof(double) : sizeof(float); }
+
+// Make the T buffers match `precision`, carrying a warm-start pressure over.
+int ensure_precision(bem_state_s* st, int precision, hipStream_t s) {
+  if (st->precision == precision) return BEM_OK;
+  hipError_t e;
+  if (st->has_p && st->precision >= 0) {
+    e = st->precision == BEM_FP64
+            ? launch_to_f64<double>((const double*)st->p, st->out64, st->n, s)
+            : launch_to_f64<float>((const float*)st->p, st->out64, st->n, s);
+    if (e != hipSuccess) return hip_fail(e, "precision change");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "precision change");
+    st->pending_import = true;
+    st->import_mask = st->has_mask;
+  }
+  free_typed(st);
+  const size_t ts = tsize(precision);
+  const size_t cs = 2 * ts;
+  int rc;
+  if ((rc = salloc(st, &st->p, st->n * ts, "pressure"))) return rc;
+  if ((rc = salloc(st, &st->t, st->n * ts, "direction"))) return rc;
+  if ((rc = salloc(st, &st->g, st->n * ts, "gap"))) return rc;
+  if ((rc = salloc(st, &st->hd, st->n * ts, "gap profile"))) return rc;
+  if ((rc = salloc(st, &st->S, (size_t)st->K->ny * st->K->g.Lx * cs, "row spectrum"))) return rc;
+  st->precision = precision;
+  return BEM_OK;
+}
+
+template <typename T>
+CgBufs<T> bufs(bem_state_s* st) {
+  return {(T*)st->p, (T*)st->t, (T*)st->g, (T*)st->hd, st->mask, (cplx<T>*)st->S, st->part,
+          st->sc};
+}
+
+struct SolveCfg {
+  double tol;
+  int max_iter;
+  int stall_limit;
+};
+
+int status_code(int st) {
+  switch (st) {
+    case CG_ST_NOCONV: return BEM_ENOCONV;
+    case CG_ST_FLOOR: return BEM_EFLOOR;
+    case CG_ST_NUMERIC: return BEM_ENUMERIC;
+    default: return BEM_OK;
+  }
+}
+
+// Run one CG solve to convergence on the device.  Returns the status code;
+// *iters receives the iterations of this solve.
+template <typename T>
+int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, double* resid,
+           hipStream_t s) {
+  CgScal* h = st->sc_host;
+  std::memset(h, 0, sizeof(CgScal));
+  h->G_old = 1.0;
+  h->best_G = 1e300;
+  h->tol = cfg.tol;
+  h->first = 1;
+  h->max_iter = cfg.max_iter;
+  h->stall_limit = cfg.stall_limit;
+  hipError_t e = hipMemcpyAsync(st->sc, h, sizeof(CgScal), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "solver scalars");
+  if ((e = launch_prepare<T>((T*)st->t, (T*)st->p, fixed_set ? st->mask : nullptr, !fixed_set,
+                             st->n, s)) != hipSuccess)
+    return hip_fail(e, "solver prepare");
+  const Geom& g = st->K->g;
+  const SpecView<T> K = spec_view<T>(st->K);
+  const CgBufs<T> b = bufs<T>(st);
+  int chunk = 4;
+  for (;;) {
+    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, chunk, s)) != hipSuccess)
+      return hip_fail(e, "CG iteration launch");
+    if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e, "solver scalars");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "CG iteration");
+    if (h->done) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  *iters = h->iter;
+  *resid = h->rhs2 > 0 ? std::sqrt(h->G / h->rhs2) : std::sqrt(h->G);
+  return status_code(h->status);
+}
+
+template <typename T>
+int finalize(bem_state_s* st, bool fixed_set, hipStream_t s) {
+  hipError_t e = launch_finalize<T>(bufs<T>(st), fixed_set, st->n, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(st->sc_host, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "final sums");
+  return BEM_OK;
+}
+
+int worse(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  return std::max(a, b);
+}
+
+// Apply an imported (or precision-converted) pressure / contact set.
+template <typename T>
+int apply_import(bem_state_s* st, hipStream_t s) {
+  if (!st->pending_import) return BEM_OK;
+  hipError_t e = launch_from_f64<T>(st->out64, (T*)st->p, st->n, s);
+  if (e != hipSuccess) return hip_fail(e, "state import");
+  st->pending_import = false;
+  st->has_p = true;
+  if (!st->import_mask) {
+    int rc = finalize<T>(st, false, s);  // contact set = {p > 0}
+    if (rc) return rc;
+  }
+  st->has_mask = true;
+  return BEM_OK;
+}
+
+template <typename T>
+int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool adhesive,
+                double pcrit, double* p_out, unsigned char* c_out, double* u_out, bool outs_host,
+                bem_result* res, hipStream_t s) {
+  bem_influence_s* K = st->K;
+  const size_t n = st->n;
+  int rc = apply_import<T>(st, s);
+  if (rc) return rc;
+  SolveCfg cfg;
+  cfg.tol = P.tol > 0 ? P.tol : (P.precision == BEM_FP64 ? 1e-12 : 1e-6);
+  cfg.max_iter = P.max_iter > 0 ? P.max_iter : 20000;
+  cfg.stall_limit = P.stall_limit > 0 ? P.stall_limit
+                                      : (P.stall_limit < 0 ? 0 : (P.precision == BEM_MIXED ? 50 : 0));
+  hipError_t e;
+  int status = BEM_OK, iters_total = 0, rounds = 0, it = 0;
+  double resid = 0.0;
+  const double inv_ck00 = 1.0 / (K->C * K->K00);
+
+  auto non_adhesive = [&](double d) -> int {
+    hipError_t ee = launch_make_hd<T>(h_dev, d, (T*)st->hd, n, s);
+    if (ee != hipSuccess) return hip_fail(ee, "gap profile");
+    if (!st->has_p) {
+      ee = launch_cold_start<T>((T*)st->p, (const T*)st->hd, inv_ck00, n, s);
+      if (ee != hipSuccess) return hip_fail(ee, "cold start");
+      st->has_p = true;
+    }
+    int r = run_cg<T>(st, false, cfg, &it, &resid, s);
+    if (r < 0) return r;
+    status = worse(status, r);
+    iters_total += it;
+    int f = finalize<T>(st, false, s);
+    if (f) return f;
+    st->has_mask = true;
+    return BEM_OK;
+  };
+
+  if (!adhesive) {
+    rc = non_adhesive(P.d);
+    if (rc) return rc;
+  } else {
+    if (!st->has_mask) {
+      rc = non_adhesive(std::max(P.d, P.d_preload));
+      if (rc) return rc;
+    }
+    if ((e = launch_make_hd<T>(h_dev, P.d, (T*)st->hd, n, s)) != hipSuccess)
+      return hip_fail(e, "gap profile");
+    for (;;) {
+      int r = run_cg<T>(st, true, cfg, &it, &resid, s);
+      if (r < 0) return r;
+      status = worse(status, r);
+      iters_total += it;
+      if ((e = launch_detach<T>(bufs<T>(st), pcrit, n, s)) != hipSuccess)
+        return hip_fail(e, "detachment");
+      if ((e = hipMemcpyAsync(st->sc_host, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+        return hip_fail(e, "detachment");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "detachment");
+      if (st->sc_host->fin_detach == 0.0) break;
+      ++rounds;
+      if (iters_total >= cfg.max_iter * 8) {
+        status = worse(status, BEM_ENOCONV);
+        break;
+      }
+    }
+    rc = finalize<T>(st, true, s);
+    if (rc) return rc;
+  }
+
+  const CgScal* h = st->sc_host;
+  if (res) {
+    res->d = P.d;
+    res->F = K->dx * K->dy * h->fin_sum_p;
+    res->n_contact = (long long)h->fin_contact;
+    res->area = (double)res->n_contact * K->dx * K->dy;
+    res->n_penetrating = adhesive ? (long long)h->fin_pen : 0;
+    res->residual = resid;
+    res->p_crit = adhesive ? pcrit : 0.0;
+    res->iters = iters_total;
+    res->detach_rounds = rounds;
+    res->status = status;
+  }
+  // outputs
+  const hipMemcpyKind kd = outs_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (p_out) {
+    const double* src;
+    if (std::is_same<T, double>::value) {
+      src = (const double*)st->p;
+    } else {
+      if ((e = launch_to_f64<T>((const T*)st->p, st->out64, n, s)) != hipSuccess)
+        return hip_fail(e, "pressure output");
+      src = st->out64;
+    }
+    if ((e = hipMemcpyAsync(p_out, src, n * sizeof(double), kd, s)) != hipSuccess)
+      return hip_fail(e, "pressure output");
+  }
+  if (c_out && (e = hipMemcpyAsync(c_out, st->mask, n, kd, s)) != hipSuccess)
+    return hip_fail(e, "contact output");
+  if (u_out) {
+    if (p_out && !std::is_same<T, double>::value) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "output");
+    }
+    if ((e = launch_u_from_gap<T>((const T*)st->g, h_dev, P.d, st->out64, n, s)) != hipSuccess)
+      return hip_fail(e, "displacement output");
+    if ((e = hipMemcpyAsync(u_out, st->out64, n * sizeof(double), kd, s)) != hipSuccess)
+      return hip_fail(e, "displacement output");
+  }
+  if (outs_host && (e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "outputs");
+  return status;
+}
+
+// ---- corrected c1 of Table 1 and its natural cubic spline in ln c1 --------
+const double kTabK[19] = {-0.9, -0.8, -0.7, -0.6, -0.5, -0.4, -0.3, -0.2, -0.1, 0.0,
+                          0.1,  0.2,  0.3,  0.4,  0.5,  0.6,  0.7,  0.8,  0.9};
+const double kTabC1[19] = {0.14, 0.31, 0.495, 0.71, 0.96, 1.24, 1.58, 1.97, 2.43, 2.97,
+                           3.66, 4.52, 5.62,  7.10, 9.15, 12.25, 17.50, 27.65, 58.00};
+
+double c1_table(double k) {
+  if (!(k > -1.0 && k < 1.0)) return std::nan("");
+  for (int i = 0; i < 19; ++i)
+    if (std::fabs(k - kTabK[i]) < 1e-12) return kTabC1[i];
+  const int n = 19;
+  double y[19], M[19], a[19], b[19], c[19], r[19];
+  for (int i = 0; i < n; ++i) y[i] = std::log(kTabC1[i]);
+  const double hh = 0.1;
+  // natural spline: M0 = Mn-1 = 0; h (M[i-1] + 4 M[i] + M[i+1]) = 6 (y[i+1] - 2y[i] + y[i-1]) / h
+  for (int i = 1; i < n - 1; ++i) {
+    a[i] = 1.0;
+    b[i] = 4.0;
+    c[i] = 1.0;
+    r[i] = 6.0 * (y[i + 1] - 2.0 * y[i] + y[i - 1]) / (hh * hh);
+  }
+  // Thomas algorithm on rows 1..n-2
+  for (int i = 2; i < n - 1; ++i) {
+    const double w = a[i] / b[i - 1];
+    b[i] -= w * c[i - 1];
+    r[i] -= w * r[i - 1];
+  }
+  M[0] = M[n - 1] = 0.0;
+  M[n - 2] = r[n - 2] / b[n - 2];
+  for (int i = n - 3; i >= 1; --i) M[i] = (r[i] - c[i] * M[i + 1]) / b[i];
+  int i = (int)std::floor((k - kTabK[0]) / hh);
+  i = std::max(0, std::min(n - 2, i));
+  const double x0 = kTabK[i], x1 = kTabK[i + 1];
+  const double A = (x1 - k) / hh, B = (k - x0) / hh;
+  const double v = A * y[i] + B * y[i + 1] +
+                   ((A * A * A - A) * M[i] + (B * B * B - B) * M[i + 1]) * hh * hh / 6.0;
+  return std::exp(v);
+}
+
+double p_crit_eq24(double k, double nu, double gamma, double dx, double E0, double c0) {
+  const double c1 = c1_table(k);
+  return std::sqrt(2.0 * E0 * gamma /
+                   (alpha_kn(k, nu) * (1.0 - nu * nu) * c1 * std::pow(c0, k) * std::pow(dx, 1.0 - k)));
+}
+
+int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, double* pcrit) {
+  if (!P) return set_error(BEM_EINVAL, "bem_solve: params is NULL");
+  if (P->precision != BEM_FP64 && P->precision != BEM_MIXED)
+    return set_error(BEM_EINVAL, "bem_solve: unknown precision %d", P->precision);
+  if (P->control == BEM_CTRL_FORCE)
+    return set_error(BEM_EUNSUPPORTED, "bem_solve: force control is not implemented");
+  if (P->control != BEM_CTRL_INDENT) return set_error(BEM_EINVAL, "bem_solve: unknown control");
+  if (!is_finite(P->d)) return set_error(BEM_EINVAL, "bem_solve: non-finite indentation");
+  if (!is_finite(P->gamma) || P->gamma < 0.0 || !is_finite(P->p_crit) || !is_finite(P->tol) ||
+      !is_finite(P->d_preload))
+    return set_error(BEM_EINVAL, "bem_solve: invalid adhesion or tolerance parameter");
+  *adhesive = P->gamma > 0.0 || P->p_crit > 0.0;
+  *pcrit = 0.0;
+  if (*adhesive) {
+    if (std::fabs(K->dx - K->dy) > 1e-12 * K->dx)
+      return set_error(BEM_EUNSUPPORTED,
+                       "bem_solve: adhesion needs square elements (Eqs. 21-24 assume dx = dy)");
+    *pcrit = P->p_crit > 0.0 ? P->p_crit : p_crit_eq24(K->k, K->nu, P->gamma, K->dx, K->E0, K->c0);
+  }
+  return BEM_OK;
+}
+
+int solve_common(bem_influence_t K, const double* h_dev, const bem_params* prm, bem_state_t state,
+                 double* p_out, unsigned char* c_out, double* u_out, bool outs_host,
+                 bem_result* res, hipStream_t s) {
+  bool adhesive;
+  double pcrit;
+  int rc = check_params(K, prm, &adhesive, &pcrit);
+  if (rc) return rc;
+  bem_state_t tmp = nullptr;
+  if (!state) {
+    rc = bem_state_create(K, &tmp);
+    if (rc) return rc;
+    state = tmp;
+  }
+  if (state->K != K) {
+    if (tmp) bem_state_free(tmp);
+    return set_error(BEM_EINVAL, "bem_solve: state belongs to another influence handle");
+  }
+  rc = ensure_precision(state, prm->precision, s);
+  if (rc == BEM_OK) {
+    rc = prm->precision == BEM_FP64
+             ? solve_typed<double>(state, h_dev, *prm, adhesive, pcrit, p_out, c_out, u_out,
+                                   outs_host, res, s)
+             : solve_typed<float>(state, h_dev, *prm, adhesive, pcrit, p_out, c_out, u_out,
+                                  outs_host, res, s);
+  }
+  if (tmp) bem_state_free(tmp);
+  return rc;
+}
+
+int upload_h(bem_state_t st, const double* h, hipStream_t s) {
+  for (size_t i = 0; i < st->n; ++i)
+    if (!is_finite(h[i])) return set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
+  hipError_t e = hipMemcpyAsync(st->h64, h, st->n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "gap profile upload");
+  return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bem_params_init(bem_params* prm) {
+  if (!prm) return;
+  std::memset(prm, 0, sizeof(*prm));
+  prm->control = BEM_CTRL_INDENT;
+  prm->precision = BEM_FP64;
+}
+
+int bem_state_create(bem_influence_t K, bem_state_t* out) {
+  clear_error();
+  if (!K || !out) return set_error(BEM_EINVAL, "bem_state_create: NULL argument");
+  auto* st = new bem_state_s();
+  st->K = K;
+  st->n = (size_t)K->nx * K->ny;
+  int rc;
+  if ((rc = salloc(st, (void**)&st->mask, st->n, "contact set")) ||
+      (rc = salloc(st, (void**)&st->h64, st->n * sizeof(double), "gap profile")) ||
+      (rc = salloc(st, (void**)&st->out64, st->n * sizeof(double), "output staging")) ||
+      (rc = salloc(st, (void**)&st->part, kPartials * sizeof(double), "partial sums")) ||
+      (rc = salloc(st, (void**)&st->sc, sizeof(CgScal), "solver scalars"))) {
+    bem_state_free(st);
+    return rc;
+  }
+  hipError_t e = hipHostMalloc((void**)&st->sc_host, sizeof(CgScal), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    bem_state_free(st);
+    return hip_fail(e, "pinned scalars");
+  }
+  e = hipMemset(st->sc, 0, sizeof(CgScal));
+  if (e == hipSuccess) e = hipMemset(st->mask, 0, st->n);
+  if (e != hipSuccess) {
+    bem_state_free(st);
+    return hip_fail(e, "state init");
+  }
+  *out = st;
+  return BEM_OK;
+}
+
+int bem_state_free(bem_state_t st) {
+  if (!st) return BEM_OK;
+  free_typed(st);
+  for (void* q : {(void*)st->mask, (void*)st->h64, (void*)st->out64, (void*)st->part, (void*)st->sc})
+    if (q) hipFree(q);
+  if (st->sc_host) hipHostFree(st->sc_host);
+  delete st;
+  return BEM_OK;
+}
+
+int bem_state_set(bem_state_t st, const double* p, const unsigned char* contact) {
+  clear_error();
+  if (!st) return set_error(BEM_EINVAL, "bem_state_set: NULL state");
+  std::vector<double> zeros;
+  if (!p) {
+    zeros.assign(st->n, 0.0);
+    p = zeros.data();
+  }
+  for (size_t i = 0; i < st->n; ++i)
+    if (!is_finite(p[i])) return set_error(BEM_EINVAL, "bem_state_set: non-finite pressure");
+  hipError_t e = hipMemcpy(st->out64, p, st->n * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess && contact) e = hipMemcpy(st->mask, contact, st->n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "bem_state_set");
+  st->pending_import = true;
+  st->import_mask = contact != nullptr;
+  st->has_p = false;
+  st->has_mask = false;
+  return BEM_OK;
+}
+
+int bem_state_get(bem_state_t st, double* p, unsigned char* contact) {
+  clear_error();
+  if (!st) return set_error(BEM_EINVAL, "bem_state_get: NULL state");
+  hipError_t e = hipSuccess;
+  if (p) {
+    if (st->pending_import) {
+      e = hipMemcpy(p, st->out64, st->n * sizeof(double), hipMemcpyDeviceToHost);
+    } else if (!st->has_p) {
+      std::memset(p, 0, st->n * sizeof(double));
+    } else {
+      e = st->precision == BEM_FP64
+              ? launch_to_f64<double>((const double*)st->p, st->out64, st->n, nullptr)
+              : launch_to_f64<float>((const float*)st->p, st->out64, st->n, nullptr);
+      if (e == hipSuccess) e = hipMemcpy(p, st->out64, st->n * sizeof(double), hipMemcpyDeviceToHost);
+    }
+  }
+  if (e == hipSuccess && contact) e = hipMemcpy(contact, st->mask, st->n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "bem_state_get");
+  return BEM_OK;
+}
+
+int bem_solve(bem_influence_t K, const double* h, const bem_params* prm, bem_state_t state,
+              double* p_out, unsigned char* contact_out, double* u_out, bem_result* res,
+              void* stream) {
+  clear_error();
+  if (!K || !h) return set_error(BEM_EINVAL, "bem_solve: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  bem_state_t tmp = nullptr;
+  int rc;
+  if (!state) {
+    if ((rc = bem_state_create(K, &tmp))) return rc;
+    state = tmp;
+  }
+  rc = upload_h(state, h, s);
+  if (rc == BEM_OK)
+    rc = solve_common(K, state->h64, prm, state, p_out, contact_out, u_out, true, res, s);
+  if (tmp) bem_state_free(tmp);
+  return rc;
+}
+
+int bem_solve_dev(bem_influence_t K, const double* h, const bem_params* prm, bem_state_t state,
+                  double* p_out, unsigned char* contact_out, double* u_out, bem_result* res,
+                  void* stream) {
+  clear_error();
+  if (!K || !h) return set_error(BEM_EINVAL, "bem_solve_dev: NULL argument");
+  return solve_common(K, h, prm, state, p_out, contact_out, u_out, false, res, (hipStream_t)stream);
+}
+
+int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const double* d_list,
+              int n_steps, bem_state_t state, bem_result* res, void* stream) {
+  clear_error();
+  if (!K || !h || !prm || !d_list || !res || n_steps < 0)
+    return set_error(BEM_EINVAL, "bem_sweep: invalid argument");
+  for (int i = 0; i < n_steps; ++i)
+    if (!is_finite(d_list[i])) return set_error(BEM_EINVAL, "bem_sweep: non-finite indentation");
+  hipStream_t s = (hipStream_t)stream;
+  bem_state_t tmp = nullptr;
+  int rc;
+  if (!state) {
+    if ((rc = bem_state_create(K, &tmp))) return rc;
+    state = tmp;
+  }
+  rc = upload_h(state, h, s);
+  int worst = BEM_OK;
+  const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
+  for (int i = 0; rc == BEM_OK && i < n_steps; ++i) {
+    bem_params P = *prm;
+    P.d = d_list[i];
+    const bool unloading = adhesive && i > 0 && d_list[i] < d_list[i - 1];
+    if (adhesive && !unloading) {
+      P.gamma = 0.0;
+      P.p_crit = 0.0;
+    }
+    int r = solve_common(K, state->h64, &P, state, nullptr, nullptr, nullptr, true, &res[i], s);
+    if (r < 0) {
+      rc = r;
+      break;
+    }
+    worst = worse(worst, r);
+  }
+  if (tmp) bem_state_free(tmp);
+  return rc < 0 ? rc : worst;
+}
+
+double bem_c1(double k) { return c1_table(k); }
+
+double bem_p_crit(double k, double nu, double gamma, double dx, double E0, double c0) {
+  if (!(k > -1.0 && k < 1.0) || !(nu >= 0.0 && nu < 0.5) || !(gamma >= 0.0) || !(dx > 0.0) ||
+      !(E0 > 0.0) || !(c0 > 0.0))
+    return std::nan("");
+  return p_crit_eq24(k, nu, gamma, dx, E0, c0);
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+"""GPU contact solves against the FP64 oracle (same seeded inputs)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import analytic as an
+from oracle import influence as inf
+from oracle import material as m
+from oracle import solver as so
+from oracle.convolution import FFTConvolver
+from paper_1612_08395_amd import inputs
+from tests.gpu_util import announce, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10     # relative L2 pressure error, all-FP64 path
+MIXED_TOL = 2e-5     # relative L2 pressure error, mixed path
+
+
+def _bem():
+    from paper_1612_08395_amd import bem
+    return bem
+
+
+def _oracle(n, L, k, nu, ny=None, L_y=None):
+    ny = ny or n
+    dx = L / n
+    Kq = inf.influence_quarter(n, ny, dx, dx, k)
+    C = m.compliance(k, nu)
+    return dx, Kq, C, FFTConvolver(Kq, C, workers=-1)
+
+
+def _count_close(a, b, frac=1e-3):
+    return abs(int(a) - int(b)) <= max(1, frac * max(a, b))
+
+
+def test_config1_hertz_type_fp64_and_mixed():
+    # 128 x 128, side 2, k = 0.5, nu = 0.3, R = 1, d = 0.01, FP64, tol 1e-12
+    bem = _bem()
+    n, L, k, nu, R, d = 128, 2.0, 0.5, 0.3, 1.0, 0.01
+    announce("config1", n, k)
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    h = inputs.parabolic(n, L, R)
+    ref = so.solve_nonadhesive(Kq, C, h, d, tol=1e-12, conv=conv)
+    K = bem.bem_influence(n, n, dx, k, nu)
+    rc, res, p, c, u = bem.bem_solve(K, h, bem.bem_params_init(d=d), want_u=True)
+    assert rc == bem.BEM_OK and res.status == 0
+    assert rel_l2(p, ref.p) <= FP64_TOL
+    assert np.array_equal(c.astype(bool), ref.contact)
+    assert res.n_contact == ref.contact.sum()
+    assert res.F == pytest.approx(so.force(ref.p, dx, dx), rel=1e-10)
+    assert rel_l2(u, ref.u) <= 1e-10
+    # closed forms of Section 2.2 (Eq. 15, reading of Eq. 16)
+    a = an.hertz_radius(k, R, d)
+    assert res.F == pytest.approx(an.hertz_force(k, nu, R, a), rel=2e-2)
+    assert abs(math.sqrt(res.area / math.pi) - a) < dx
+    # mixed path
+    rc, rm, pm, cm, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, precision=bem.BEM_MIXED))
+    assert rm.status in (0, bem.BEM_EFLOOR)
+    assert rel_l2(pm, ref.p) <= MIXED_TOL
+    assert _count_close(rm.n_contact, ref.contact.sum())
+    K.free()
+
+
+@pytest.mark.parametrize("ny,nx,k,shape", [(37, 50, -0.5, "parabolic"), (64, 64, 0.0, "cone"),
+                                           (33, 33, 0.8, "parabolic"), (1, 16, 0.2, "parabolic")])
+def test_ragged_and_degenerate_grids(ny, nx, k, shape):
+    bem = _bem()
+    announce("ragged", ny, nx, k, shape)
+    nu, L = 0.3, 1.0
+    dx = L / max(nx, ny)
+    Kq = inf.influence_quarter(nx, ny, dx, dx, k)
+    C = m.compliance(k, nu)
+    xs = (np.arange(nx) + 0.5) * dx - 0.45 * L
+    ys = (np.arange(ny) + 0.5) * dx - 0.55 * L * ny / max(nx, ny)
+    r = np.hypot(xs[None, :], ys[:, None])
+    h = r * r / 2.0 if shape == "parabolic" else 0.1 * r
+    d = float(np.quantile(h, 0.15))
+    ref = so.solve_nonadhesive(Kq, C, h, d, tol=1e-12)
+    K = bem.bem_influence(nx, ny, dx, k, nu)
+    rc, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d))
+    assert rel_l2(p, ref.p) <= FP64_TOL
+    assert np.array_equal(c.astype(bool), ref.contact)
+    K.free()
+
+
+def test_no_contact_and_full_contact():
+    bem = _bem()
+    announce("degenerate-contact")
+    n, L, k, nu = 32, 1.0, 0.3, 0.3
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    K = bem.bem_influence(n, n, dx, k, nu)
+    h = inputs.parabolic(n, L, 1.0)
+    # indenter above the surface: no contact, zero pressure
+    rc, res, p, c, _ = bem.bem_solve(K, h + 0.01, bem.bem_params_init(d=0.0))
+    assert res.n_contact == 0 and np.all(p == 0) and res.F == 0.0
+    # flat rigid plane pushed in everywhere: whole grid in contact
+    flat = np.zeros((n, n))
+    ref = so.solve_nonadhesive(Kq, C, flat, 1e-3, tol=1e-12, conv=conv)
+    rc, res, p, c, _ = bem.bem_solve(K, flat, bem.bem_params_init(d=1e-3))
+    assert res.n_contact == n * n == ref.contact.sum()
+    assert rel_l2(p, ref.p) <= FP64_TOL
+    K.free()
+
+
+def test_warm_start_state_roundtrip_and_sweep():
+    bem = _bem()
+    announce("warm-start")
+    n, L, k, nu, R = 96, 1.0, -0.3, 0.25, 1.0
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    h = inputs.parabolic(n, L, R)
+    K = bem.bem_influence(n, n, dx, k, nu)
+    st = bem.bem_state_create(K)
+    ds = [0.004, 0.008, 0.012]
+    refs = [so.solve_nonadhesive(Kq, C, h, d, tol=1e-12, conv=conv) for d in ds]
+    iters = []
+    for d, ref in zip(ds, refs):
+        rc, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d), state=st)
+        assert rel_l2(p, ref.p) <= FP64_TOL
+        iters.append(res.iters)
+    # export / import of the state
+    p_s, c_s = bem.bem_state_get(st)
+    assert rel_l2(p_s, refs[-1].p) <= FP64_TOL
+    st2 = bem.bem_state_create(K)
+    bem.bem_state_set(st2, p_s, c_s)
+    rc, res2, p2, c2, _ = bem.bem_solve(K, h, bem.bem_params_init(d=ds[-1]), state=st2)
+    assert rel_l2(p2, refs[-1].p) <= FP64_TOL
+    assert res2.iters <= 2
+    # the sweep entry point gives the same forces
+    rc, sw = bem.bem_sweep(K, h, bem.bem_params_init(), ds)
+    for r, ref in zip(sw, refs):
+        assert r.F == pytest.approx(so.force(ref.p, dx, dx), rel=1e-10)
+    st.free()
+    st2.free()
+    K.free()
+
+
+def test_adhesive_step_transitions_parity():
+    # Section 3.1: non-adhesive preload, then pull-off steps with the
+    # detachment criterion; each step compared with the oracle's own step.
+    bem = _bem()
+    announce("adhesive-transitions")
+    n, L, k, nu, R, gam = 96, 1.0, 0.5, 0.3, 1.0, 5e-4
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    h = inputs.parabolic(n, L, R)
+    pc = m.p_crit(k, nu, gam, dx)
+    assert bem.bem_p_crit(k, nu, gam, dx) == pytest.approx(pc, rel=1e-14)
+    d0 = 0.02
+    ref = so.solve_nonadhesive(Kq, C, h, d0, tol=1e-12, conv=conv)
+    K = bem.bem_influence(n, n, dx, k, nu)
+    st = bem.bem_state_create(K)
+    rc, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d0), state=st)
+    assert rel_l2(p, ref.p) <= FP64_TOL
+    A, pr = ref.contact, ref.p
+    compared = 0
+    d = d0
+    for s in range(12):
+        d -= 0.004
+        step = so.adhesive_step(Kq, C, h, d, A, pr, pc, tol=1e-12, conv=conv)
+        rc, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, gamma=gam), state=st)
+        assert res.p_crit == pytest.approx(pc, rel=1e-14)
+        if not np.array_equal(c.astype(bool), step.contact):
+            # a near-tie detachment decision: compare counts only, then stop
+            assert _count_close(res.n_contact, step.contact.sum())
+            break
+        assert rel_l2(p, step.p) <= FP64_TOL
+        assert res.F == pytest.approx(so.force(step.p, dx, dx), rel=1e-9, abs=1e-12)
+        assert np.all(-p[c.astype(bool)] <= pc * (1 + 1e-12))
+        assert res.n_penetrating == 0
+        compared += 1
+        A, pr = step.contact, step.p
+        if not A.any():
+            break
+    assert compared >= 5
+    st.free()
+    K.free()
+
+
+def test_error_paths():
+    bem = _bem()
+    announce("errors")
+    K = bem.bem_influence_ex(16, 16, 0.1, 0.12, 0.3, 0.3)
+    h = np.zeros((16, 16))
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_solve(K, h, bem.bem_params_init(d=0.01, control=bem.BEM_CTRL_FORCE, F=1.0))
+    assert e.value.code == bem.BEM_EUNSUPPORTED
+    with pytest.raises(bem.BemError) as e:      # adhesion on non-square elements
+        bem.bem_solve(K, h, bem.bem_params_init(d=0.01, gamma=1e-3))
+    assert e.value.code == bem.BEM_EUNSUPPORTED
+    hb = h.copy()
+    hb[3, 4] = np.nan
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_solve(K, hb, bem.bem_params_init(d=0.01))
+    assert e.value.code == bem.BEM_EINVAL
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_solve(K, h, bem.bem_params_init(d=float("inf")))
+    assert e.value.code == bem.BEM_EINVAL
+    # iteration limit: warning status, last iterate returned
+    Kq = bem.bem_influence(64, 64, 1 / 64, 0.0, 0.3)
+    rc, res, p, c, _ = bem.bem_solve(Kq, inputs.parabolic(64, 1.0, 1.0),
+                                     bem.bem_params_init(d=0.01, max_iter=3))
+    assert rc == bem.BEM_ENOCONV and res.status == bem.BEM_ENOCONV and res.iters == 3
+    assert np.all(np.isfinite(p))
+    K.free()
+    Kq.free()
