@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""FFT-CG contact solves/s at 2048^2 on one MI355X: mixed (FP32 transforms and
+vectors, FP64 reductions) vs all-FP64.
+
+Workload: non-adhesive contact of a self-affine rough surface with a
+power-law graded half-space (Li & Popov, arXiv:1612.08395, Section 2.2,
+rough-surface example), on a 2048 x 2048 grid (4096 x 4096 padded
+transform): k = 0.3, nu = 0.3, side L = 1, Gaussian heights with
+C(q) ~ q^-2(1+H), H = 0.7, roll-off q0 = 8 (2 pi / L), cut-off
+q1 = 512 (2 pi / L), rms height 1e-3 L, seed 1612.  One bench step is an
+indentation sweep of 20 depths d_s = s d10 / 20 (d10: depth of 10 % contact
+area), each a full CG solve warm-started from the previous depth, with the
+gap profile resident in HBM.  value = solves per second of the mixed path.
+
+Prints one JSON line.  Also reports the FP64 path, the mixed-vs-FP64
+pressure error per depth, the roofline of the dominant kernel and the FP64
+CPU oracle timed on the host cores (bounded sample).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+METRIC = "FFT-CG contact solves/s & HBM GB/s at 2048² (FP32 vs FP64); serving p99 latency"
+N, L, K_EXP, NU = 2048, 1.0, 0.3, 0.3
+H_EXP, Q0, Q1, RMS, SEED = 0.7, 8.0, 512.0, 1e-3, 1612
+N_DEPTHS, AREA_FRAC = 20, 0.10
+# Depth of 10 % contact area, found by bisection on the FP64 GPU path
+# (`python bench.py --find-d10`); None: find it before the timed region.
+D10 = None
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "col_conv_f32_2048_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload():
+    from paper_1612_08395_amd import inputs
+    two_pi = 2.0 * math.pi / L
+    return inputs.fractal_gap(N, L, H_EXP, Q0 * two_pi, Q1 * two_pi, RMS * L, SEED)
+
+
+def find_d10(bem, K, h_dev, torch):
+    """Bisection on the FP64 path for 10 % contact area (to 1 % of it)."""
+    import numpy as np  # noqa
+    hmax = float(h_dev.max().item())
+    lo, hi = 0.0, hmax
+    st = bem.bem_state_create(K)
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        _, res = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=mid), state=st)
+        frac = res.n_contact / float(N * N)
+        log(f"[d10] d={mid:.6e} area={frac:.5f} iters={res.iters}")
+        if abs(frac - AREA_FRAC) <= 0.01 * AREA_FRAC:
+            st.free()
+            return mid
+        if frac < AREA_FRAC:
+            lo = mid
+        else:
+            hi = mid
+    st.free()
+    return 0.5 * (lo + hi)
+
+
+def run_sweep(bem, K, h_dev, depths, precision, keep_p=False, torch=None):
+    st = bem.bem_state_create(K)
+    out = []
+    p_list = []
+    for d in depths:
+        prm = bem.bem_params_init(d=d, precision=precision)
+        if keep_p:
+            p = torch.empty((N, N), dtype=torch.float64, device="cuda")
+            _, res = bem.bem_solve_dev(K, h_dev, prm, state=st, p_out=p)
+            p_list.append(p)
+        else:
+            _, res = bem.bem_solve_dev(K, h_dev, prm, state=st)
+        out.append(res.as_dict())
+    st.free()
+    return out, p_list
+
+
+def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
+    for _ in range(warmup):
+        run_sweep(bem, K, h_dev, depths, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        r, _ = run_sweep(bem, K, h_dev, depths, precision)
+        results.append(r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0), results
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("conv_kernels.h", "fft_lds.h", "common.h", "launch.h", "conv.hip"):
+        with open(os.path.join(HERE, "paper_1612_08395_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def roofline(bem, K, torch):
+    """Dominant kernel: the fused column sweep (FFT x spectrum x IFFT), FP32.
+    Algorithmic bytes per launch: read + write the ny x Lx complex row
+    spectrum and read the (Lx+1) x (Ly+1) real kernel spectrum."""
+    info = K.info
+    Lx, Ly = info.Mx // 2, info.My // 2
+    bytes_per_launch = 2 * info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
+    stream = torch.cuda.current_stream()
+    ms = bem.bem_kernel_time(K, bem.BEM_MIXED, 1, reps=50, stream=stream)
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_sha") == kernel_source_sha():
+            traffic = tr.get("bytes_per_launch")
+    other = {}
+    for which, name in ((0, "row_r2c"), (2, "row_c2r")):
+        t = bem.bem_kernel_time(K, bem.BEM_MIXED, which, reps=50, stream=stream)
+        b = info.ny * info.nx * 4 + info.ny * Lx * 8
+        other[name] = {"ms": round(t, 5), "GB/s": round(b / (t * 1e-3) / 1e9, 1)}
+    return {"bound": "hbm", "kernel": "k_col_conv<float,2048,4,512>", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "ms_per_launch": round(ms, 5),
+            "algorithmic_bytes_per_launch": bytes_per_launch, "other_sweeps": other}
+
+
+def cpu_baseline(h, depths, iters_per_solve, sample_iters):
+    """The FP64 oracle on the host cores: `sample_iters` CG iterations of the
+    first depth, scaled to solves/s with the GPU FP64 mean iterations/solve."""
+    from oracle import influence as inf
+    from oracle import material as m
+    from oracle import solver as so
+    from oracle.convolution import FFTConvolver
+    cores = os.cpu_count() or 1
+    dx = L / N
+    t_setup = time.perf_counter()
+    Kq = inf.influence_quarter(N, N, dx, dx, K_EXP)
+    conv = FFTConvolver(Kq, m.compliance(K_EXP, NU), workers=cores)
+    t_setup = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    so.solve_nonadhesive(Kq, m.compliance(K_EXP, NU), h, depths[-1], tol=1e-12,
+                         max_iter=sample_iters, conv=conv)
+    t = time.perf_counter() - t0
+    # sample_iters iterations plus one extra convolution at the final check
+    per_iter = t / (sample_iters + 0.5)
+    return {"value": round(1.0 / (per_iter * iters_per_solve), 5), "unit": "solves/s",
+            "cores": cores, "kind": "oracle",
+            "sample": (f"{sample_iters} CG iterations of the FP64 oracle (numpy/scipy.fft, "
+                       f"{cores} workers) at 2048^2, depth d10, {t:.1f} s; scaled by the GPU "
+                       f"FP64 mean of {iters_per_solve:.1f} iterations/solve; influence "
+                       f"setup {t_setup:.1f} s not counted"),
+            "s_per_iter": round(per_iter, 4)}
+
+
+def profile_kernels(bem, torch):
+    """Few launches of each sweep kernel at 2048^2 (for rocprofv3 --pmc) and a
+    plain device copy of 2^28 floats (1 GiB read + 1 GiB written) whose
+    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    K = bem.bem_influence(N, N, L / N, K_EXP, NU)
+    out = {}
+    for prec, name in ((bem.BEM_MIXED, "f32"), (bem.BEM_FP64, "f64")):
+        for which, kname in ((0, "row_r2c"), (1, "col_conv"), (2, "row_c2r")):
+            out[f"{kname}_{name}_ms"] = bem.bem_kernel_time(K, prec, which, reps=4)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_bytes_each_way"] = 4 << 28
+    print(json.dumps(out), flush=True)
+    K.free()
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--find-d10", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
+                         "and a 1 GiB device copy, for hardware-counter runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import torch
+    from paper_1612_08395_amd import bem
+    torch.cuda.set_device(0)
+    if args.profile_kernels:
+        return profile_kernels(bem, torch)
+    log("[bench] building workload")
+    h = workload()
+    h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
+    K = bem.bem_influence(N, N, L / N, K_EXP, NU)
+    d10 = D10
+    if d10 is None or args.find_d10:
+        d10 = find_d10(bem, K, h_dev, torch)
+        log(f"[bench] d10 = {d10!r}")
+        if args.find_d10:
+            print(json.dumps({"d10": d10}), flush=True)
+            return 0
+    depths = [d10 * s / N_DEPTHS for s in range(1, N_DEPTHS + 1)]
+
+    # accuracy of the mixed path against the FP64 path, per depth (untimed)
+    log("[bench] mixed vs FP64 pressures")
+    r64, p64 = run_sweep(bem, K, h_dev, depths, bem.BEM_FP64, keep_p=True, torch=torch)
+    r32, p32 = run_sweep(bem, K, h_dev, depths, bem.BEM_MIXED, keep_p=True, torch=torch)
+    err = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(p32, p64)]
+    cnt = [abs(x["n_contact"] - y["n_contact"]) / max(1, y["n_contact"]) for x, y in zip(r32, r64)]
+    del p64, p32
+
+    log("[bench] timed mixed sweeps")
+    t32, res32 = timed(bem, K, h_dev, depths, bem.BEM_MIXED, args.steps, args.warmup, torch)
+    log("[bench] timed FP64 sweeps")
+    t64, res64 = timed(bem, K, h_dev, depths, bem.BEM_FP64, args.fp64_steps, 0, torch)
+    it32 = [x["iters"] for x in res32[-1]]
+    it64 = [x["iters"] for x in res64[-1]]
+    solves32 = N_DEPTHS * args.steps / t32
+    solves64 = N_DEPTHS * args.fp64_steps / t64
+    ms_step = t32 / args.steps * 1e3
+    # whole-loop effective bandwidth: 124 algorithmic bytes per element per CG
+    # iteration (FP32 path, fused design), 248 for FP64
+    loop32 = 124.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
+    loop64 = 248.0 * N * N * sum(it64) / (t64 / args.fp64_steps) / 1e9
+
+    log("[bench] roofline")
+    roof = roofline(bem, K, torch)
+    out = {
+        "metric": METRIC, "value": round(solves32, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rough-surface indentation sweep 2048^2 (4096^2 padded), "
+                               "k=0.3 nu=0.3, 20 depths to 10% contact, mixed precision",
+                   "n": N, "padded": 2 * N, "k": K_EXP, "nu": NU, "H": H_EXP,
+                   "q0_over_2pi_L": Q0, "q1_over_2pi_L": Q1, "rms_over_L": RMS, "seed": SEED,
+                   "depths_per_step": N_DEPTHS, "d10": d10},
+        "roofline": roof,
+        "fp64": {"value": round(solves64, 3), "unit": "solves/s", "steps": args.fp64_steps,
+                 "ms_per_step": round(t64 / args.fp64_steps * 1e3, 3),
+                 "iters_per_solve": round(sum(it64) / len(it64), 2),
+                 "loop_GBps_algorithmic": round(loop64, 1)},
+        "iters_per_solve": round(sum(it32) / len(it32), 2),
+        "loop_GBps_algorithmic": round(loop32, 1),
+        "mixed_vs_fp64": {"rel_l2_pressure_per_depth": [float(f"{e:.3e}") for e in err],
+                          "contact_count_rel_diff_per_depth": [float(f"{c:.2e}") for c in cnt],
+                          "status_mixed": sorted({x["status"] for x in res32[-1]})},
+        "contact_area_final": res32[-1][-1]["n_contact"] / float(N * N),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(h, depths, sum(it64) / len(it64), args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    K.free()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

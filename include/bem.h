@@ -222,6 +222,17 @@ double bem_c1(double k);
  * bem_c1 (NaN on invalid arguments). */
 double bem_p_crit(double k, double nu, double gamma, double dx, double E0, double c0);
 
+/*
+ * bem_kernel_time -- measurement hook: average duration (ms, from two HIP
+ * events on `stream`) of `reps` back-to-back launches of one sweep of the
+ * convolution of Eq. 13 on the handle's grid: which = 0 row R2C transform,
+ * 1 column transform x kernel spectrum x inverse transform, 2 row C2R
+ * transform.  Runs on a zero field in the handle's scratch buffers (same
+ * kernels and launch shapes as the solver's sweeps).  Synchronises `stream`.
+ */
+int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void* stream,
+                    double* avg_ms);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* bem_last_error(void);
 

@@ -316,3 +316,15 @@ def bem_c1(k):
 
 def bem_p_crit(k, nu, gamma, dx, E0=1.0, c0=1.0):
     return _f_p_crit(float(k), float(nu), float(gamma), float(dx), float(E0), float(c0))
+
+
+_f_kernel_time = _sig("bem_kernel_time", _c_int, [_vp, _c_int, _c_int, _c_int, _vp,
+                                                  ctypes.POINTER(_c_double)])
+
+
+def bem_kernel_time(K, precision, which, reps=20, stream=None):
+    """Average ms of one convolution sweep kernel (0 R2C, 1 column, 2 C2R)."""
+    ms = _c_double()
+    _check(_f_kernel_time(K.handle, int(precision), int(which), int(reps), _stream(stream),
+                          ctypes.byref(ms)))
+    return ms.value

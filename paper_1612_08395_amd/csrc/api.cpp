@@ -181,4 +181,15 @@ int bem_convolve(bem_influence_t K, const double* p, double* u, void* stream) {
   return BEM_OK;
 }
 
+int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void* stream,
+                    double* avg_ms) {
+  clear_error();
+  if (!K || !avg_ms) return set_error(BEM_EINVAL, "bem_kernel_time: NULL argument");
+  if (precision != BEM_FP64 && precision != BEM_MIXED)
+    return set_error(BEM_EINVAL, "bem_kernel_time: unknown precision %d", precision);
+  if (which < 0 || which > 2 || reps < 1)
+    return set_error(BEM_EINVAL, "bem_kernel_time: which in {0,1,2}, reps >= 1");
+  return sweep_time(K, precision, which, reps, (hipStream_t)stream, avg_ms);
+}
+
 }  // extern "C"

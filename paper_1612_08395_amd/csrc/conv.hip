@@ -48,6 +48,30 @@ hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cp
   });
 }
 
+template <typename T>
+hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T* p, T* u,
+                        cplx<T>* S, hipStream_t s) {
+  if (which == 1) return launch_col<T>(g, K, S, nullptr, s);
+  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+    constexpr int L = decltype(LX)::value;
+    constexpr int NT = row_threads(L);
+    if (which == 0) {
+      PlainLoad<T> pro{p, g.nx};
+      hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
+                         pro, S, g.nx, g.ny, K.twx);
+    } else {
+      PlainStore<T> epi{u, g.nx};
+      hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0,
+                         s, S, g.nx, g.ny, K.twx, epi);
+    }
+    return hipGetLastError();
+  });
+}
+
+template hipError_t launch_sweep<float>(const Geom&, const SpecView<float>&, int, const float*,
+                                        float*, cplx<float>*, hipStream_t);
+template hipError_t launch_sweep<double>(const Geom&, const SpecView<double>&, int, const double*,
+                                         double*, cplx<double>*, hipStream_t);
 template hipError_t launch_col<float>(const Geom&, const SpecView<float>&, cplx<float>*, const int*,
                                       hipStream_t);
 template hipError_t launch_col<double>(const Geom&, const SpecView<double>&, cplx<double>*,

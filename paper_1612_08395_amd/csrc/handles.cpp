@@ -67,7 +67,7 @@ int influence_build(bem_influence_s* h) {
 
 void influence_release(bem_influence_s* h) {
   void* ptrs[] = {h->Kq, h->KT64, h->KT32, h->twx64, h->twy64, h->twx32,
-                  h->twy32, h->S64, h->S32, h->io64};
+                  h->twy32, h->S64, h->S32, h->io64, h->io32};
   for (void* p : ptrs)
     if (p) hipFree(p);
   h->device_bytes = 0;
@@ -95,6 +95,54 @@ int convolve_device(bem_influence_s* h, int precision, const void* p, void* u, h
     e = launch_conv<float>(h->g, spec_view<float>(h), (const float*)p, (float*)u, h->S32, s);
   }
   if (e != hipSuccess) return hip_fail(e, "convolution launch");
+  return BEM_OK;
+}
+
+int sweep_time(bem_influence_s* h, int precision, int which, int reps, hipStream_t s, double* ms) {
+  const size_t n = (size_t)h->nx * h->ny;
+  const size_t ns = (size_t)h->ny * h->g.Lx;
+  int rc;
+  hipError_t e;
+  if (precision == BEM_FP64) {
+    if ((rc = ensure_io(h))) return rc;
+    if (!h->S64 && (rc = dev_alloc(h, (void**)&h->S64, ns * sizeof(cplx<double>), "scratch")))
+      return rc;
+  } else {
+    if (!h->io32 && (rc = dev_alloc(h, (void**)&h->io32, n * sizeof(float), "scratch"))) return rc;
+    if (!h->S32 && (rc = dev_alloc(h, (void**)&h->S32, ns * sizeof(cplx<float>), "scratch")))
+      return rc;
+  }
+  // defined inputs: zero field and spectrum
+  if (precision == BEM_FP64) {
+    e = hipMemsetAsync(h->io64, 0, n * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->S64, 0, ns * sizeof(cplx<double>), s);
+  } else {
+    e = hipMemsetAsync(h->io32, 0, n * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->S32, 0, ns * sizeof(cplx<float>), s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel timing setup");
+  hipEvent_t a, b;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = hipEventCreate(&b)) != hipSuccess) {
+    hipEventDestroy(a);
+    return hip_fail(e, "event");
+  }
+  // one untimed launch, then `reps` timed back-to-back launches
+  for (int r = -1; r < reps && e == hipSuccess; ++r) {
+    if (r == 0) e = hipEventRecord(a, s);
+    if (e != hipSuccess) break;
+    e = precision == BEM_FP64
+            ? launch_sweep<double>(h->g, spec_view<double>(h), which, h->io64, h->io64, h->S64, s)
+            : launch_sweep<float>(h->g, spec_view<float>(h), which, h->io32, h->io32, h->S32, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "kernel timing");
+  *ms = (double)t / reps;
   return BEM_OK;
 }
 

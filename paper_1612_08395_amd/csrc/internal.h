@@ -25,6 +25,7 @@ struct bem_influence_s {
   bem::cplx<double>* S64 = nullptr;
   bem::cplx<float>* S32 = nullptr;
   double* io64 = nullptr;
+  float* io32 = nullptr;
 };
 
 namespace bem {
@@ -39,6 +40,7 @@ int influence_build(bem_influence_s* h);
 void influence_release(bem_influence_s* h);
 int ensure_io(bem_influence_s* h);
 int convolve_device(bem_influence_s* h, int precision, const void* p, void* u, hipStream_t s);
+int sweep_time(bem_influence_s* h, int precision, int which, int reps, hipStream_t s, double* ms);
 
 int dev_alloc(bem_influence_s* h, void** p, size_t bytes, const char* what);
 

@@ -92,6 +92,11 @@ template <typename T>
 hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int* done,
                       hipStream_t s);
 
+// One sweep of the convolution on its own: 0 row R2C, 1 column, 2 row C2R.
+template <typename T>
+hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T* p, T* u,
+                        cplx<T>* S, hipStream_t s);
+
 template <typename T>
 hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cplx<T>* S,
                        hipStream_t s);

@@ -131,13 +131,18 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
   const SpecView<T> K = spec_view<T>(st->K);
   const CgBufs<T> b = bufs<T>(st);
   int chunk = 4;
+  long long queued = 0;
   for (;;) {
     if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, chunk, s)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
+    queued += chunk;
     if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
       return hip_fail(e, "solver scalars");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "CG iteration");
     if (h->done) break;
+    // the device stops itself at max_iter; this only guards the host loop
+    if (queued > (long long)cfg.max_iter + 256)
+      return set_error(BEM_EDEVICE, "CG loop did not report completion");
     chunk = std::min(chunk * 2, 32);
   }
   *iters = h->iter;
