@@ -164,6 +164,31 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
             "s_per_iter": round(per_iter, 4)}
 
 
+def serving(count, slots, bem):
+    """Request stream of mixed grids (64^2..1024^2), k, indenters, 50 %
+    adhesive: saturation throughput of each path, then Poisson arrivals at
+    0.8 x the FP64 saturation rate for both paths."""
+    from paper_1612_08395_amd import inputs
+    from paper_1612_08395_amd.serving import run_stream
+    reqs = inputs.serving_requests(count, 2024)
+    out = {"requests": count, "slots": slots, "budget_bytes": 8 << 30}
+    sat = {}
+    for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        s = run_stream(reqs, prec, None, slots)
+        sat[name] = s["solves_per_s"]
+        out[f"{name}_saturation"] = {k: s[k] for k in ("solves_per_s", "p50_latency_s",
+                                                       "p99_latency_s", "peak_running",
+                                                       "cache_hits", "cache_misses", "evictions",
+                                                       "status_counts")}
+    qps = 0.8 * sat["fp64"]
+    for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        s = run_stream(reqs, prec, qps, slots, seed=7)
+        out[f"{name}_poisson"] = {k: s[k] for k in ("offered_qps", "solves_per_s", "p50_latency_s",
+                                                    "p99_latency_s", "mean_wait_s", "peak_running",
+                                                    "status_counts")}
+    return out
+
+
 def profile_kernels(bem, torch):
     """Few launches of each sweep kernel at 2048^2 (for rocprofv3 --pmc) and a
     plain device copy of 2^28 floats (1 GiB read + 1 GiB written) whose
@@ -193,6 +218,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--find-d10", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests per serving run (0: skip the serving measurement)")
+    ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
                          "and a 1 GiB device copy, for hardware-counter runs")
@@ -266,6 +294,9 @@ def main():
                           "status_mixed": sorted({x["status"] for x in res32[-1]})},
         "contact_area_final": res32[-1][-1]["n_contact"] / float(N * N),
     }
+    if args.serving_requests > 0:
+        log("[bench] serving")
+        out["serving"] = serving(args.serving_requests, args.serving_slots, bem)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(h, depths, sum(it64) / len(it64), args.cpu_iters)

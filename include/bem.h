@@ -168,6 +168,9 @@ int bem_state_free(bem_state_t st);
  * in contact (NULL on set: p > 0). */
 int bem_state_set(bem_state_t st, const double* p, const unsigned char* contact);
 int bem_state_get(bem_state_t st, double* p, unsigned char* contact);
+/* Forget the warm-start data: the next solve starts cold, exactly as with a
+ * fresh state (buffers are kept). */
+int bem_state_reset(bem_state_t st);
 
 /*
  * bem_solve -- one contact solve at indentation prm->d for the gap profile h
@@ -221,6 +224,59 @@ double bem_c1(double k);
 /* Detachment stress of Eq. 24 for square elements of side dx, with c1 from
  * bem_c1 (NaN on invalid arguments). */
 double bem_p_crit(double k, double nu, double gamma, double dx, double E0, double c0);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent solves on one GPU
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes of an influence handle and of one solver state for a grid,
+ * as the server's admission control counts them. */
+int bem_footprint(int nx, int ny, int precision, long long* influence_bytes,
+                  long long* state_bytes);
+
+typedef struct bem_server_s* bem_server_t;
+
+typedef struct {
+  int nx, ny;                 /* grid and material: the influence cache key */
+  double dx, dy, k, nu, E0, c0;
+  const double* h;            /* host ny x nx gap profile, copied at submit */
+  bem_params prm;             /* indentation, adhesion, precision, tolerances */
+  double* p_out;              /* optional host ny x nx pressure output; must stay valid
+                                 until bem_server_poll reports the request done */
+  unsigned char* contact_out; /* optional host ny x nx contact output (same rule) */
+} bem_request;
+
+typedef struct {
+  long long completed, failed, queued;
+  int running, peak_running;
+  double p50_latency_s, p99_latency_s;  /* submit -> result, completed requests */
+  double mean_wait_s;                   /* submit -> start */
+  double solves_per_s;                  /* completed / (last completion - first submit) */
+  long long device_bytes_reserved, cache_entries, cache_hits, cache_misses, evictions;
+} bem_server_stats_t;
+
+/*
+ * bem_server_create -- a request loop with n_slots (1..16) concurrent solves,
+ * each on its own non-blocking HIP stream of the current device, and a
+ * device-memory budget for cached influence operators plus solver states
+ * (bem_footprint).  Each request is a cold-start bem_solve of its own;
+ * requests run concurrently on the GPU and a queued request starts as soon
+ * as a slot is free and the budget admits it (FIFO; idle cache entries are
+ * evicted least-recently-used).  The result of a request does not depend
+ * on what else runs.
+ */
+int bem_server_create(long long budget_bytes, int n_slots, bem_server_t* out);
+/* Queue a request; *id identifies it.  BEM_ENOMEM if it can never fit the
+ * budget, BEM_EINVAL for a bad grid. */
+int bem_server_submit(bem_server_t srv, const bem_request* req, long long* id);
+/* Returns 1 while the request is pending (wait = 0), else 0 with *res and
+ * *status (the bem_solve status) filled in; the id is then released.  With
+ * wait != 0 blocks until the request is done. */
+int bem_server_poll(bem_server_t srv, long long id, int wait, bem_result* res, int* status);
+int bem_server_stats(bem_server_t srv, bem_server_stats_t* out);
+int bem_server_reset_stats(bem_server_t srv);
+/* Stops the workers after their current solves; queued requests are dropped. */
+int bem_server_free(bem_server_t srv);
 
 /*
  * bem_kernel_time -- measurement hook: average duration (ms, from two HIP

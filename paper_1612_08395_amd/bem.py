@@ -328,3 +328,109 @@ def bem_kernel_time(K, precision, which, reps=20, stream=None):
     _check(_f_kernel_time(K.handle, int(precision), int(which), int(reps), _stream(stream),
                           ctypes.byref(ms)))
     return ms.value
+
+
+# ---- serving -----------------------------------------------------------------
+
+class Request(ctypes.Structure):
+    _fields_ = [("nx", _c_int), ("ny", _c_int), ("dx", _c_double), ("dy", _c_double),
+                ("k", _c_double), ("nu", _c_double), ("E0", _c_double), ("c0", _c_double),
+                ("h", _dp), ("prm", Params), ("p_out", _dp), ("contact_out", _u8p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("queued", ctypes.c_longlong), ("running", _c_int), ("peak_running", _c_int),
+                ("p50_latency_s", _c_double), ("p99_latency_s", _c_double),
+                ("mean_wait_s", _c_double), ("solves_per_s", _c_double),
+                ("device_bytes_reserved", ctypes.c_longlong),
+                ("cache_entries", ctypes.c_longlong), ("cache_hits", ctypes.c_longlong),
+                ("cache_misses", ctypes.c_longlong), ("evictions", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_llp = ctypes.POINTER(ctypes.c_longlong)
+_f_state_reset = _sig("bem_state_reset", _c_int, [_vp])
+_f_footprint = _sig("bem_footprint", _c_int, [_c_int, _c_int, _c_int, _llp, _llp])
+_f_server_create = _sig("bem_server_create", _c_int, [ctypes.c_longlong, _c_int,
+                                                      ctypes.POINTER(_vp)])
+_f_server_submit = _sig("bem_server_submit", _c_int, [_vp, ctypes.POINTER(Request), _llp])
+_f_server_poll = _sig("bem_server_poll", _c_int, [_vp, ctypes.c_longlong, _c_int,
+                                                  ctypes.POINTER(Result), ctypes.POINTER(_c_int)])
+_f_server_stats = _sig("bem_server_stats", _c_int, [_vp, ctypes.POINTER(ServerStats)])
+_f_server_reset_stats = _sig("bem_server_reset_stats", _c_int, [_vp])
+_f_server_free = _sig("bem_server_free", _c_int, [_vp])
+
+
+def bem_state_reset(st):
+    _check(_f_state_reset(st.handle))
+
+
+def bem_footprint(nx, ny, precision):
+    a, b = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(_f_footprint(int(nx), int(ny), int(precision), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+class Server:
+    """Owning wrapper of bem_server_t.  Keeps each submitted request's host
+    arrays alive until the request has been polled."""
+
+    def __init__(self, budget_bytes, n_slots):
+        h = _vp()
+        _check(_f_server_create(int(budget_bytes), int(n_slots), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def submit(self, nx, ny, dx, k, nu, h, prm, dy=None, E0=1.0, c0=1.0, want_p=False):
+        h = _host(h, (ny, nx))
+        p = np.empty((ny, nx)) if want_p else None
+        c = np.empty((ny, nx), dtype=np.uint8) if want_p else None
+        req = Request(nx, ny, dx, dx if dy is None else dy, k, nu, E0, c0,
+                      h.ctypes.data_as(_dp), prm,
+                      p.ctypes.data_as(_dp) if p is not None else None,
+                      c.ctypes.data_as(_u8p) if c is not None else None)
+        rid = ctypes.c_longlong()
+        _check(_f_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = (p, c)
+        return rid.value
+
+    def poll(self, rid, wait=True):
+        """None while pending (wait=False), else (status, Result, p, contact)."""
+        res = Result()
+        st = _c_int()
+        rc = _f_server_poll(self._h, int(rid), 1 if wait else 0, ctypes.byref(res), ctypes.byref(st))
+        _check(rc)
+        if rc == 1:
+            return None
+        p, c = self._keep.pop(rid)
+        return st.value, res, p, c
+
+    def stats(self):
+        s = ServerStats()
+        _check(_f_server_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def reset_stats(self):
+        _check(_f_server_reset_stats(self._h))
+
+    def free(self):
+        if self._h:
+            _f_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def bem_server_create(budget_bytes, n_slots):
+    return Server(budget_bytes, n_slots)

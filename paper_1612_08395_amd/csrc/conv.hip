@@ -2,7 +2,18 @@
 #include "conv_kernels.h"
 #include "launch.h"
 
+#include <stdlib.h>
+
 namespace bem {
+
+int col_width_cap() {
+  static const int cap = [] {
+    const char* v = getenv("BEM_COL_WIDTH");
+    const int c = v ? atoi(v) : 16;
+    return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 16;
+  }();
+  return cap;
+}
 
 template <typename T>
 hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int* done,

@@ -107,6 +107,16 @@ __global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restri
   pro.template finish<NTHR>(red);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that XCD x works on the contiguous block range
+// [x nb/8, (x+1) nb/8): adjacent column groups, which share the 128-byte
+// lines of the row spectrum, then run on the same XCD and their partial-line
+// reads and writes meet in one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  if (nb & 7) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // Multiply the transformed columns held in LDS by the kernel spectrum.
 template <typename T, int LY, int W, int NTHR, int STR>
 __device__ __forceinline__ void col_multiply(cplx<T>* lds, int c0, int lx, const T* __restrict__ KT,
@@ -160,7 +170,7 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
   if (done && *done) return;
   constexpr int STR = lds_len(LY);
   __shared__ cplx<T> lds[2 * W * STR];
-  const int c0 = blockIdx.x * W;
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
   for (int f = threadIdx.x; f < W * LY; f += NTHR) {
     const int c = f % W, n = f / W;
     cplx<T> x = {T(0), T(0)};

@@ -40,12 +40,17 @@ __host__ __device__ constexpr int col_width_lds(int LY) {
   return w;
 }
 
+// Tuning knob: BEM_COL_WIDTH (1, 2, 4, 8, 16) caps the column-group width.
+int col_width_cap();
+
 template <typename T>
 inline int col_width(int LY, int lx) {
   int w = col_width_lds<T>(LY);
   int wmax = 1;
   while (wmax * 2 <= 16 && lx / (wmax * 2) >= 256) wmax *= 2;
-  return w < wmax ? w : wmax;
+  if (w > wmax) w = wmax;
+  const int cap = col_width_cap();
+  return w < cap ? w : cap;
 }
 
 __host__ __device__ constexpr int col_threads(int W, int LY) {

@@ -445,6 +445,13 @@ int bem_state_free(bem_state_t st) {
   return BEM_OK;
 }
 
+int bem_state_reset(bem_state_t st) {
+  clear_error();
+  if (!st) return set_error(BEM_EINVAL, "bem_state_reset: NULL state");
+  st->has_p = st->has_mask = st->pending_import = st->import_mask = false;
+  return BEM_OK;
+}
+
 int bem_state_set(bem_state_t st, const double* p, const unsigned char* contact) {
   clear_error();
   if (!st) return set_error(BEM_EINVAL, "bem_state_set: NULL state");

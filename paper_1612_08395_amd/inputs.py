@@ -79,7 +79,7 @@ def fractal_surface(n, L, H, q0, q1, rms, seed):
     qy = 2.0 * math.pi * np.fft.fftfreq(n, d=L / n)
     q = np.hypot(qx[None, :], qy[:, None])
     expo = -2.0 * (1.0 + H)
-    C = np.where(q < q0, q0 ** expo, np.where(q <= q1, np.maximum(q, 1e-300) ** expo, 0.0))
+    C = np.where(q <= q1, np.maximum(q, q0) ** expo, 0.0)
     C[0, 0] = 0.0
     z = np.fft.irfft2(W * np.sqrt(C), s=(n, n))
     z -= z.mean()
@@ -98,3 +98,63 @@ def random_pressure(n_y, n_x, seed, scale=1.0):
     """Non-negative random pressure field for convolution tests."""
     rng = np.random.default_rng(seed)
     return scale * rng.random((n_y, n_x))
+
+
+def serving_requests(count, seed, nu=0.3, mu_tabor=5.0):
+    """A stream of independent solve requests of mixed size, material and
+    indenter (all seeded):
+
+    * grid n = round(2^U(6, 10)) snapped to a multiple of 16, side L = 1;
+    * k uniform on the 0.05 grid inside (-0.8, 0.8) (so influence operators
+      can be reused), nu fixed;
+    * indenter, uniformly: paraboloid R = 1 with target contact radius
+      a ~ U(0.1, 0.25) (depth a^2 / ((1+k) R), Eq. 15 of the paper), cone of
+      slope 0.1 with d ~ U(0.005, 0.02), flat punch of radius L/4 with
+      d ~ U(1e-3, 1e-2), or a rough surface (H ~ U(0.5, 0.9), q0 =
+      min(8, n/16) 2 pi / L, q1 = (n/4) 2 pi / L, rms 1e-3, depth at the 5 %
+      height quantile);
+    * half of the requests adhesive: work of adhesion from a Tabor-like
+      parameter mu = (R gamma^2 / (E*^2 dx^3))^(1/3) = 5 with R = 1 and the
+      grid spacing as interaction range; non-adhesive preload to d0, then one
+      pull-off solve at d0 / 2.
+    Returns a list of dicts (n, k, shape, h, d, d_preload, gamma).
+    """
+    rng = np.random.default_rng(seed)
+    ks = np.round(np.arange(-15, 16) * 0.05, 10)
+    estar = 1.0 / (1.0 - nu * nu)
+    surfaces = {}
+    out = []
+    for i in range(count):
+        n = int(round(2.0 ** rng.uniform(6.0, 10.0) / 16.0)) * 16
+        n = max(64, min(1024, n))
+        k = float(rng.choice(ks))
+        shape = ["parabolic", "cone", "punch", "rough"][int(rng.integers(0, 4))]
+        L = 1.0
+        if shape == "parabolic":
+            a = rng.uniform(0.1, 0.25)
+            h = parabolic(n, L, 1.0)
+            d = a * a / ((1.0 + k) * 1.0)
+        elif shape == "cone":
+            h = cone(n, L, 0.1)
+            d = rng.uniform(0.005, 0.02)
+        elif shape == "punch":
+            h = flat_punch(n, L, L / 4)
+            d = rng.uniform(1e-3, 1e-2)
+        else:
+            key = (n, int(rng.integers(0, 8)))
+            if key not in surfaces:
+                H = 0.5 + 0.4 * ((key[1] + 0.5) / 8.0)
+                surfaces[key] = fractal_gap(n, L, H, min(8.0, n / 16.0) * 2 * math.pi / L,
+                                            (n / 4.0) * 2 * math.pi / L, 1e-3 * L, 7919 * n + key[1])
+            h = surfaces[key]
+            d = float(np.quantile(h, 0.05))
+        adhesive = bool(rng.integers(0, 2))
+        req = {"n": n, "k": k, "shape": shape, "h": h}
+        if adhesive:
+            dx = L / n
+            req.update(d=0.5 * d, d_preload=d,
+                       gamma=math.sqrt(mu_tabor ** 3 * estar * estar * dx ** 3 / 1.0))
+        else:
+            req.update(d=d, d_preload=0.0, gamma=0.0)
+        out.append(req)
+    return out
