@@ -33,7 +33,7 @@ H_EXP, Q0, Q1, RMS, SEED = 0.7, 8.0, 512.0, 1e-3, 1612
 N_DEPTHS, AREA_FRAC = 20, 0.10
 # Depth of 10 % contact area, found by bisection on the FP64 GPU path
 # (`python bench.py --find-d10`); None: find it before the timed region.
-D10 = None
+D10 = 0.004669638031382314
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "col_conv_f32_2048_traffic.json")
 
@@ -103,7 +103,8 @@ def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("conv_kernels.h", "fft_lds.h", "common.h", "launch.h", "conv.hip"):
+    for f in ("conv_kernels.h", "fft_lds.h", "wave_fft.h", "col_wave.h", "common.h", "launch.h",
+              "conv.hip"):
         with open(os.path.join(HERE, "paper_1612_08395_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -19,18 +19,22 @@
 // row sweeps of the two convolutions:
 //   K1 row R2C   prologue UpdatePro : update p from the previous tau, t, g
 //   K2 column    (fused spectrum multiply)
-//   K3 row C2R   epilogue GapEpi    : g = u + (h - d), G, convergence test
-//   K4 row R2C   prologue DirPro    : new direction t
+//   K3 row C2R   epilogue GapEpi    : g = u + (h - d), sums for G
+//   K4 row R2C   prologue DirPro    : convergence decision, new direction t
 //   K5 column
-//   K6 row C2R   epilogue DotsEpi   : sum g t, sum r t, tau (r is not stored)
+//   K6 row C2R   epilogue DotsEpi   : sum g t, sum r t (r is not stored)
 // Since t = 0 off Ic, the sums of K6 need no mask.
 //
-// Reductions are FP64: per-thread sums, a fixed-order block reduction, one
-// partial per workgroup, and the last workgroup to finish (ticket counter)
-// adds the partials in index order -- bitwise reproducible, no floating
-// point atomics.  Scalars live in CgScal in device memory; every kernel
-// returns at once when `done` is set, so the host may queue several
-// iterations and check the flag rarely.
+// Reductions are FP64 and the iteration kernels use no atomics or fences:
+// every reducing kernel writes one partial per workgroup (fixed-order block
+// sum) into its own buffer, and the kernel that needs the total adds the
+// partials again at its start, in index order, in every workgroup.  The
+// result is bitwise reproducible, identical in all workgroups, and made
+// visible by the kernel boundary.  The iteration index `it` is a kernel
+// argument; K4 makes the convergence decision (every workgroup reaches the
+// same one, workgroup 0 records it) and keeps G_old and the stagnation state
+// in slots indexed by it & 1.  Every kernel returns at once when `done` is
+// set, so the host may queue several iterations and check the flag rarely.
 #pragma once
 #include "common.h"
 #include "conv_kernels.h"
@@ -38,18 +42,78 @@
 namespace bem {
 
 struct CgScal {
-  double G, G_old, rhs2, ratio, tau, delta;
-  double sum_dp, sum_p, gt, rt, best_G, tol;
-  double n_ol;
+  double tol;
+  int max_iter, stall_limit;
+  // K4, workgroup 0, slot it & 1
+  double G_hist[2], best_hist[2];
+  int stall_hist[2];
+  // decision record (written once, when done is set)
+  int done, status, iter, pad_;
+  double G, rhs2, sum_p;
+  // final sums of the elementwise kernels
   double fin_sum_p, fin_contact, fin_pen, fin_detach;
-  int first, done, status, iter, stall, max_iter, stall_limit, pad_;
   unsigned int ticket[8];
 };
 
 enum { CG_ST_OK = 0, CG_ST_NOCONV = 1, CG_ST_FLOOR = 2, CG_ST_NUMERIC = -5 };
 
-// Reduce NV per-thread values over the grid; returns true in the last
-// workgroup, where tot[] holds the grid totals (valid in every thread).
+// partial-sum slots inside the `part` allocation
+constexpr int kMaxRowBlocks = 2048;
+constexpr int kPartUpd = 0;                      // 3 values: sum|dp|, sum|p|, n_ol
+constexpr int kPartGap = 3 * kMaxRowBlocks;      // 2 values: sum_Ic g^2, sum_Ic (h-d)^2
+constexpr int kPartDots = 5 * kMaxRowBlocks;     // 2 values: sum g t, sum r t
+constexpr int kPartElem = 7 * kMaxRowBlocks;     // elementwise kernels (3 values x 1024)
+constexpr int kPartTotal = kPartElem + 3 * 1024;
+
+// Block sums of NV values (result in every thread), one barrier pair.
+template <int NV, int NTHR>
+__device__ __forceinline__ void block_sum_n(double (&v)[NV], double* red) {
+  constexpr int NW = NTHR / 64;
+  static_assert(NV * NW <= 64, "reduction scratch");
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * NW + w] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += red[k * NW + i];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// This workgroup's partials (plain stores; read by later kernels).
+template <int NV, int NTHR>
+__device__ __forceinline__ void write_partials(double (&acc)[NV], double* red, double* part) {
+  block_sum_n<NV, NTHR>(acc, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[blockIdx.x * NV + k] = acc[k];
+}
+
+// Totals of the nb partials an earlier kernel wrote (same order everywhere).
+template <int NV, int NTHR>
+__device__ __forceinline__ void read_totals(const double* __restrict__ part, int nb, double* red,
+                                            double (&tot)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < nb; i += NTHR)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] += part[i * NV + k];
+  block_sum_n<NV, NTHR>(tot, red);
+}
+
+// Last-workgroup reduction, used only by the once-per-solve elementwise
+// kernels (agent-scope stores, fence, ticket).
 template <int NV, int NTHR>
 __device__ __forceinline__ bool grid_reduce_last(const double (&acc)[NV], double* red,
                                                  double* part, unsigned int* ticket,
@@ -57,7 +121,8 @@ __device__ __forceinline__ bool grid_reduce_last(const double (&acc)[NV], double
   __shared__ int am_last;
   double s[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) s[v] = block_sum<NTHR>(acc[v], red);
+  for (int v = 0; v < NV; ++v) s[v] = acc[v];
+  block_sum_n<NV, NTHR>(s, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -71,184 +136,326 @@ __device__ __forceinline__ bool grid_reduce_last(const double (&acc)[NV], double
   if (!am_last) return false;
   __threadfence();
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += NTHR)
-      a += __hip_atomic_load(&part[i * NV + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tot[v] = block_sum<NTHR>(a, red);
-  }
+  for (int v = 0; v < NV; ++v) tot[v] = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTHR)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      tot[v] += __hip_atomic_load(&part[i * NV + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  block_sum_n<NV, NTHR>(tot, red);
   if (threadIdx.x == 0) *ticket = 0u;
   return true;
 }
 
-template <typename T, bool FS>
+// K1 prologue: p update with the previous iteration's tau, t and g.
+template <typename T, bool FS, int PER>
 struct UpdatePro {
   T* p;
   const T* t;
   const T* g;
   const uint8_t* mask;
-  CgScal* sc;
+  const CgScal* sc;
   double* part;
-  int nx;
+  int nx, nb, it;
   double tau, a_dp, a_p, a_ol;
-  int first;
-  __device__ bool skip() const { return sc->done != 0; }
-  __device__ void begin() {
-    first = sc->first;
-    tau = sc->tau;
+  template <int NTHR>
+  __device__ bool begin(double* red) {
+    if (sc->done) return false;
     a_dp = a_p = a_ol = 0.0;
-  }
-  __device__ T load(int y, int x) {
-    const size_t i = (size_t)y * nx + x;
-    const T po = p[i];
-    if (first) {
-      a_p += fabs((double)po);
-      return po;
+    tau = 0.0;
+    if (it > 0) {
+      double tot[2];
+      read_totals<2, NTHR>(part + kPartDots, nb, red, tot);
+      tau = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
     }
+    return true;
+  }
+  __device__ __forceinline__ T upd(T po, T tv, T gv, bool in_set) {
     double pn = (double)po;
     if constexpr (FS) {
-      if (mask[i]) pn = (double)po - tau * (double)t[i];
+      if (in_set) pn = (double)po - tau * (double)tv;
     } else {
-      if (po > T(0)) pn = (double)po - tau * (double)t[i];
+      if (po > T(0)) pn = (double)po - tau * (double)tv;
       if (pn < 0.0) pn = 0.0;
-      const double gv = (double)g[i];
-      if (pn == 0.0 && gv < 0.0) {
-        pn = -tau * gv;
+      if (pn == 0.0 && gv < T(0)) {
+        pn = -tau * (double)gv;
         a_ol += 1.0;
       }
     }
     const T pt = (T)pn;
-    p[i] = pt;
     a_dp += fabs((double)pt - (double)po);
     a_p += fabs((double)pt);
     return pt;
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
-    const double acc[3] = {a_dp, a_p, a_ol};
-    double tot[3];
-    if (grid_reduce_last<3, NTHR>(acc, red, part, &sc->ticket[0], tot) && threadIdx.x == 0) {
-      sc->sum_dp = tot[0];
-      sc->sum_p = tot[1];
-      sc->n_ol = tot[2];
-      if (first) {
-        sc->delta = 0.0;
-      } else {
-        sc->delta = (FS || tot[2] == 0.0) ? 1.0 : 0.0;
-        sc->iter += 1;
+  __device__ void load(int ya, int yb, bool hasb, int nxl, T (&va)[PER], T (&vb)[PER]) {
+    T ta[PER], tb[PER], ga[PER], gb[PER];
+    bool ma[PER], mb[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t ia = (size_t)ya * nx + n, ib = (size_t)yb * nx + n;
+      va[q] = in ? p[ia] : T(0);
+      vb[q] = inb ? p[ib] : T(0);
+      ta[q] = tb[q] = ga[q] = gb[q] = T(0);
+      ma[q] = mb[q] = false;
+      if (it > 0) {
+        ta[q] = in ? t[ia] : T(0);
+        tb[q] = inb ? t[ib] : T(0);
+        if constexpr (FS) {
+          ma[q] = in && mask[ia];
+          mb[q] = inb && mask[ib];
+        } else {
+          ga[q] = in ? g[ia] : T(0);
+          gb[q] = inb ? g[ib] : T(0);
+        }
+      }
+    }
+    if (it == 0) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) a_p += fabs((double)va[q]) + fabs((double)vb[q]);
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      if (n < nxl) {
+        va[q] = upd(va[q], ta[q], ga[q], ma[q]);
+        if (hasb) vb[q] = upd(vb[q], tb[q], gb[q], mb[q]);
       }
     }
   }
+  template <int NTHR>
+  __device__ void commit(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
+                         const T (&vb)[PER]) {
+    if (it == 0) return;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      if (n < nxl) {
+        p[(size_t)ya * nx + n] = va[q];
+        if (hasb) p[(size_t)yb * nx + n] = vb[q];
+      }
+    }
+  }
+  template <int NTHR>
+  __device__ void finish(double* red) {
+    double acc[3] = {a_dp, a_p, a_ol};
+    write_partials<3, NTHR>(acc, red, part + kPartUpd);
+  }
 };
 
-template <typename T, bool FS>
+// K3 epilogue: g = u + (h - d) and the partial sums of g^2, (h - d)^2 on Ic.
+template <typename T, bool FS, int PER>
 struct GapEpi {
   T* g;
   const T* hd;
   const T* p;
   const uint8_t* mask;
-  CgScal* sc;
+  const CgScal* sc;
   double* part;
   int nx;
+  T ha[PER], hb[PER];
+  bool ca[PER], cb[PER];
   double a_G, a_r;
-  __device__ bool skip() const { return sc->done != 0; }
-  __device__ void begin() { a_G = a_r = 0.0; }
-  __device__ void store(int y, int x, T u) {
-    const size_t i = (size_t)y * nx + x;
-    const double h = (double)hd[i];
-    const T gv = (T)((double)u + h);
-    g[i] = gv;
-    const bool in = FS ? (mask[i] != 0) : (p[i] > T(0));
-    if (in) {
-      a_G += (double)gv * (double)gv;
-      a_r += h * h;
+  template <int NTHR>
+  __device__ bool begin(double*) { return sc->done == 0; }
+  template <int NTHR>
+  __device__ void prefetch(int ya, int yb, bool hasb, int nxl) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
+      ha[q] = in ? hd[a] : T(0);
+      hb[q] = inb ? hd[b] : T(0);
+      if constexpr (FS) {
+        ca[q] = in && mask[a];
+        cb[q] = inb && mask[b];
+      } else {
+        ca[q] = in && p[a] > T(0);
+        cb[q] = inb && p[b] > T(0);
+      }
     }
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
-    const double acc[2] = {a_G, a_r};
-    double tot[2];
-    if (grid_reduce_last<2, NTHR>(acc, red, part, &sc->ticket[1], tot) && threadIdx.x == 0) {
-      const double G = tot[0];
-      sc->G = G;
-      sc->rhs2 = tot[1];
-      int done = 0, status = CG_ST_OK;
-      if (!isfinite(G) || !isfinite(sc->sum_p)) {
-        done = 1;
-        status = CG_ST_NUMERIC;
-      } else if (!sc->first && sqrt(G) <= sc->tol * sqrt(tot[1]) && sc->n_ol == 0.0 &&
-                 sc->sum_dp <= sc->tol * sc->sum_p) {
-        done = 1;
-      } else if (sc->iter >= sc->max_iter) {
-        done = 1;
-        status = CG_ST_NOCONV;
-      } else if (sc->stall_limit > 0) {
-        if (G < sc->best_G) {
-          sc->best_G = G;
-          sc->stall = 0;
-        } else if (++sc->stall >= sc->stall_limit) {
-          done = 1;
-          status = CG_ST_FLOOR;
+  __device__ void consume(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
+                          const T (&vb)[PER]) {
+    double aG = 0.0, ar = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      if (n < nxl) {
+        const T ga = (T)((double)va[q] + (double)ha[q]);
+        g[(size_t)ya * nx + n] = ga;
+        if (ca[q]) {
+          aG += (double)ga * (double)ga;
+          ar += (double)ha[q] * (double)ha[q];
+        }
+        if (hasb) {
+          const T gb = (T)((double)vb[q] + (double)hb[q]);
+          g[(size_t)yb * nx + n] = gb;
+          if (cb[q]) {
+            aG += (double)gb * (double)gb;
+            ar += (double)hb[q] * (double)hb[q];
+          }
         }
       }
-      if (!done) {
-        sc->ratio = (sc->G_old > 0.0) ? sc->delta * (G / sc->G_old) : 0.0;
-        sc->G_old = G;
-        sc->first = 0;
-      }
-      sc->status = status;
-      sc->done = done;
     }
+    a_G = aG;
+    a_r = ar;
+  }
+  template <int NTHR>
+  __device__ void finish(double* red) {
+    double acc[2] = {a_G, a_r};
+    write_partials<2, NTHR>(acc, red, part + kPartGap);
   }
 };
 
-template <typename T, bool FS>
+// K4 prologue: convergence decision (stopping test at the current iterate,
+// iteration limit, non-finite values, MIXED stagnation), then t.
+template <typename T, bool FS, int PER>
 struct DirPro {
   T* t;
   const T* g;
   const T* p;
   const uint8_t* mask;
-  const CgScal* sc;
-  int nx;
+  CgScal* sc;
+  double* part;
+  int nx, nb, it;
   double ratio;
-  __device__ bool skip() const { return sc->done != 0; }
-  __device__ void begin() { ratio = sc->ratio; }
-  __device__ T load(int y, int x) {
-    const size_t i = (size_t)y * nx + x;
-    const bool in = FS ? (mask[i] != 0) : (p[i] > T(0));
-    const T tn = in ? (T)((double)g[i] + ratio * (double)t[i]) : T(0);
-    t[i] = tn;
-    return tn;
+  template <int NTHR>
+  __device__ bool begin(double* red) {
+    if (sc->done) return false;
+    double up[3], gp[2];
+    read_totals<3, NTHR>(part + kPartUpd, nb, red, up);
+    read_totals<2, NTHR>(part + kPartGap, nb, red, gp);
+    const double G = gp[0], rhs2 = gp[1];
+    const double sum_dp = up[0], sum_p = up[1], n_ol = up[2];
+    const double G_old = it > 0 ? sc->G_hist[(it - 1) & 1] : 1.0;
+    double best = it > 0 ? sc->best_hist[(it - 1) & 1] : 1e300;
+    int stall = it > 0 ? sc->stall_hist[(it - 1) & 1] : 0;
+    int done = 0, status = CG_ST_OK;
+    if (!isfinite(G) || !isfinite(sum_p)) {
+      done = 1;
+      status = CG_ST_NUMERIC;
+    } else if (it > 0 && sqrt(G) <= sc->tol * sqrt(rhs2) && n_ol == 0.0 &&
+               sum_dp <= sc->tol * sum_p) {
+      done = 1;
+    } else if (it >= sc->max_iter) {
+      done = 1;
+      status = CG_ST_NOCONV;
+    } else if (sc->stall_limit > 0) {
+      if (G < best) {
+        best = G;
+        stall = 0;
+      } else if (++stall >= sc->stall_limit) {
+        done = 1;
+        status = CG_ST_FLOOR;
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (done) {
+        sc->status = status;
+        sc->iter = it;
+        sc->G = G;
+        sc->rhs2 = rhs2;
+        sc->sum_p = sum_p;
+        sc->done = 1;
+      } else {
+        sc->G_hist[it & 1] = G;
+        sc->best_hist[it & 1] = best;
+        sc->stall_hist[it & 1] = stall;
+      }
+    }
+    if (done) return false;
+    const double delta = (it == 0) ? 0.0 : ((FS || n_ol == 0.0) ? 1.0 : 0.0);
+    ratio = (G_old > 0.0) ? delta * (G / G_old) : 0.0;
+    return true;
+  }
+  template <int NTHR>
+  __device__ void load(int ya, int yb, bool hasb, int nxl, T (&va)[PER], T (&vb)[PER]) {
+    T ga[PER], gb[PER], ta[PER], tb[PER];
+    bool ca[PER], cb[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
+      ga[q] = in ? g[a] : T(0);
+      gb[q] = inb ? g[b] : T(0);
+      ta[q] = in ? t[a] : T(0);
+      tb[q] = inb ? t[b] : T(0);
+      if constexpr (FS) {
+        ca[q] = in && mask[a];
+        cb[q] = inb && mask[b];
+      } else {
+        ca[q] = in && p[a] > T(0);
+        cb[q] = inb && p[b] > T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      va[q] = ca[q] ? (T)((double)ga[q] + ratio * (double)ta[q]) : T(0);
+      vb[q] = cb[q] ? (T)((double)gb[q] + ratio * (double)tb[q]) : T(0);
+    }
+  }
+  template <int NTHR>
+  __device__ void commit(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
+                         const T (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      if (n < nxl) {
+        t[(size_t)ya * nx + n] = va[q];
+        if (hasb) t[(size_t)yb * nx + n] = vb[q];
+      }
+    }
   }
   template <int NTHR>
   __device__ void finish(double*) {}
 };
 
-template <typename T>
+// K6 epilogue: sum g t and sum r t (t = 0 off Ic, so no mask is needed).
+template <typename T, int PER>
 struct DotsEpi {
   const T* g;
   const T* t;
-  CgScal* sc;
+  const CgScal* sc;
   double* part;
   int nx;
+  T ga_[PER], gb_[PER], ta_[PER], tb_[PER];
   double a_gt, a_rt;
-  __device__ bool skip() const { return sc->done != 0; }
-  __device__ void begin() { a_gt = a_rt = 0.0; }
-  __device__ void store(int y, int x, T r) {
-    const size_t i = (size_t)y * nx + x;
-    const double tv = (double)t[i];
-    a_gt += (double)g[i] * tv;
-    a_rt += (double)r * tv;
+  template <int NTHR>
+  __device__ bool begin(double*) { return sc->done == 0; }
+  template <int NTHR>
+  __device__ void prefetch(int ya, int yb, bool hasb, int nxl) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
+      ga_[q] = in ? g[a] : T(0);
+      ta_[q] = in ? t[a] : T(0);
+      gb_[q] = inb ? g[b] : T(0);
+      tb_[q] = inb ? t[b] : T(0);
+    }
+  }
+  template <int NTHR>
+  __device__ void consume(int, int, bool, int, const T (&va)[PER], const T (&vb)[PER]) {
+    double gt = 0.0, rt = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      gt += (double)ga_[q] * (double)ta_[q] + (double)gb_[q] * (double)tb_[q];
+      rt += (double)va[q] * (double)ta_[q] + (double)vb[q] * (double)tb_[q];
+    }
+    a_gt = gt;
+    a_rt = rt;
   }
   template <int NTHR>
   __device__ void finish(double* red) {
-    const double acc[2] = {a_gt, a_rt};
-    double tot[2];
-    if (grid_reduce_last<2, NTHR>(acc, red, part, &sc->ticket[2], tot) && threadIdx.x == 0) {
-      sc->gt = tot[0];
-      sc->rt = tot[1];
-      sc->tau = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
-    }
+    double acc[2] = {a_gt, a_rt};
+    write_partials<2, NTHR>(acc, red, part + kPartDots);
   }
 };
 
@@ -315,7 +522,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_finalize(const T* __restrict__ p
   }
   const double acc[3] = {sp, nc, npen};
   double tot[3];
-  if (grid_reduce_last<3, EW_THREADS>(acc, red, part, &sc->ticket[3], tot) && threadIdx.x == 0) {
+  if (grid_reduce_last<3, EW_THREADS>(acc, red, part + kPartElem, &sc->ticket[3], tot) && threadIdx.x == 0) {
     sc->fin_sum_p = tot[0];
     sc->fin_contact = tot[1];
     sc->fin_pen = tot[2];
@@ -340,7 +547,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_detach(T* __restrict__ p, uint8_
   }
   const double acc[1] = {cnt};
   double tot[1];
-  if (grid_reduce_last<1, EW_THREADS>(acc, red, part, &sc->ticket[4], tot) && threadIdx.x == 0)
+  if (grid_reduce_last<1, EW_THREADS>(acc, red, part + kPartElem, &sc->ticket[4], tot) && threadIdx.x == 0)
     sc->fin_detach = tot[0];
 }
 

@@ -25,15 +25,16 @@ inline int ew_blocks(size_t n) {
 }
 
 template <typename T, bool FS>
-hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
+hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int it,
                                hipStream_t s) {
   const int nrp = (g.ny + 1) / 2;
   hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    UpdatePro<T, FS> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, FS>>), dim3(nrp), dim3(NT), 0, s, up, b.S,
-                       g.nx, g.ny, K.twx);
+    constexpr int PER = row_per<L, NT>();
+    UpdatePro<T, FS, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, up,
+                       b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -41,18 +42,20 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
   e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    GapEpi<T, FS> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, FS>>), dim3(nrp), dim3(NT), 0, s, b.S, g.nx,
-                       g.ny, K.twx, ge);
+    constexpr int PER = row_per<L, NT>();
+    GapEpi<T, FS, PER> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
+                       g.nx, g.ny, K.twx, ge);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
   e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    DirPro<T, FS> dp{b.t, b.g, b.p, b.mask, b.sc, g.nx};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, FS>>), dim3(nrp), dim3(NT), 0, s, dp, b.S,
-                       g.nx, g.ny, K.twx);
+    constexpr int PER = row_per<L, NT>();
+    DirPro<T, FS, PER> dp{b.t, b.g, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, dp,
+                       b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -60,19 +63,21 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
   return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    DotsEpi<T> de{b.g, b.t, b.sc, b.part, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T>>), dim3(nrp), dim3(NT), 0, s, b.S, g.nx,
-                       g.ny, K.twx, de);
+    constexpr int PER = row_per<L, NT>();
+    DotsEpi<T, PER> de{b.g, b.t, b.sc, b.part, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
+                       g.nx, g.ny, K.twx, de);
     return hipGetLastError();
   });
 }
 
+// Queue iterations it0 .. it0 + n - 1.
 template <typename T>
 hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
-                                bool fixed_set, int n, hipStream_t s) {
+                                bool fixed_set, int it0, int n, hipStream_t s) {
   for (int i = 0; i < n; ++i) {
-    hipError_t e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, s)
-                             : launch_cg_iteration<T, false>(g, K, b, s);
+    hipError_t e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, it0 + i, s)
+                             : launch_cg_iteration<T, false>(g, K, b, it0 + i, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -137,7 +142,7 @@ hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, s
 
 #define BEM_INSTANTIATE_CG(T)                                                                    \
   template hipError_t launch_cg_iterations<T>(const Geom&, const SpecView<T>&, const CgBufs<T>&, \
-                                              bool, int, hipStream_t);                           \
+                                              bool, int, int, hipStream_t);                      \
   template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \
   template hipError_t launch_cold_start<T>(T*, const T*, double, size_t, hipStream_t);           \
   template hipError_t launch_prepare<T>(T*, T*, const uint8_t*, bool, size_t, hipStream_t);      \

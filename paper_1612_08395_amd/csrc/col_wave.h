@@ -1,0 +1,112 @@
+// Fused column sweep (column FFT x kernel spectrum x inverse FFT) on wave
+// FFTs, FP32, Ly = 64 P with P in {32, 64}.
+//
+// A workgroup owns NC adjacent spectrum columns and runs 2 NC waves: for
+// column j, wave 2j transforms the even-bin half (DFT of x) and wave 2j+1
+// the odd-bin half (DFT of x w^n) of the My-point pruned transform (see
+// conv_kernels.h).  Steps: (1) the NC columns are staged through LDS with
+// coalesced row-segment loads; (2) each wave takes its column in the time
+// layout (lane l, register m = row l + 64 m); (3) forward wave FFT; (4)
+// multiply by the kernel spectrum at each register's frequency; column 0
+// (packed DC / Nyquist) pairs bins k and -k through LDS; (5) inverse wave
+// FFT; (6) the odd-half wave hands conj(w^n) o[n] to its partner through
+// LDS, the even-half wave adds it; (7) coalesced row-segment stores.
+// Workgroup barriers only around the shared staging and combine steps; the
+// transposes use each wave's private region.
+#pragma once
+#include "conv_kernels.h"
+#include "wave_fft.h"
+
+namespace bem {
+
+template <int LY, int NC>
+__global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict__ S, int lx,
+                                                         int ny, const float* __restrict__ KT,
+                                                         int kpitch,
+                                                         const cplx<float>* __restrict__ tw,
+                                                         const cplx<float>* __restrict__ twl,
+                                                         const int* __restrict__ done) {
+  constexpr int P = LY / 64;
+  constexpr int REG = wave_region<P>();
+  constexpr int NT = 128 * NC;
+  __shared__ cplx<float> lds[2 * NC * REG];
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jc = wv >> 1, parity = wv & 1;
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC;
+  const int c = c0 + jc;
+  cplx<float>* reg = lds + wv * REG;
+
+  // (1) stage the NC columns (rows < LY; zero beyond ny) into the even regions
+  for (int f = threadIdx.x; f < NC * LY; f += NT) {
+    const int cc = f % NC, n = f / NC;
+    cplx<float> x = {0.f, 0.f};
+    if (n < ny) x = S[(size_t)n * lx + c0 + cc];
+    lds[(2 * cc) * REG + n] = x;
+  }
+  __syncthreads();
+  // (2) time layout
+  cplx<float> v[P];
+  const cplx<float>* src = lds + (2 * jc) * REG;
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = src[lane + 64 * m];
+  __syncthreads();
+  if (parity) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = cmul(v[m], tw[lane + 64 * m]);
+  }
+  // (3)
+  wave_fft_fwd<float, P>(v, reg, twl, lane);
+  // (4) spectrum multiply; K(ky) is even: K(ky) = K(2 LY - ky)
+  if (c != 0) {
+    const float* Kc = KT + (size_t)c * kpitch;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int ky = 2 * wave_freq<P>(lane, r) + parity;
+      const int kq = ky <= LY ? ky : 2 * LY - ky;
+      v[r] = cscale(v[r], Kc[kq]);
+    }
+  }
+  // packed column 0: Z'[k] = ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]); bins
+  // k and -k of one parity half sit in different lanes, so swap via the
+  // wave's LDS region
+  if (c == 0) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
+    wave_lds_sync();
+    const float* K0 = KT;
+    const float* K1 = KT + (size_t)lx * kpitch;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int f = wave_freq<P>(lane, r);
+      const int fp = parity ? (LY - 1 - f) : ((LY - f) & (LY - 1));
+      const cplx<float> z1 = reg[fp];
+      const int ky = 2 * f + parity;
+      const int kq = ky <= LY ? ky : 2 * LY - ky;
+      const float a = 0.5f * (K0[kq] + K1[kq]), b = 0.5f * (K0[kq] - K1[kq]);
+      v[r] = {a * v[r].x + b * z1.x, a * v[r].y - b * z1.y};
+    }
+    wave_lds_sync();
+  }
+  // (5)
+  wave_fft_inv<float, P>(v, reg, twl, lane);
+  // (6) combine the two halves: y[n] = e[n] + conj(w^n) o[n]
+  if (parity) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) reg[lane + 64 * m] = cmulc(v[m], tw[lane + 64 * m]);
+  }
+  __syncthreads();
+  if (!parity) {
+    const cplx<float>* o = reg + REG;
+#pragma unroll
+    for (int m = 0; m < P; ++m) reg[lane + 64 * m] = cadd(v[m], o[lane + 64 * m]);
+  }
+  __syncthreads();
+  // (7)
+  for (int f = threadIdx.x; f < NC * ny; f += NT) {
+    const int cc = f % NC, n = f / NC;
+    S[(size_t)n * lx + c0 + cc] = lds[(2 * cc) * REG + n];
+  }
+}
+
+}  // namespace bem

@@ -1,8 +1,11 @@
 // Plain convolution u = C K * p (Eq. 13 with zero padding), FP32 and FP64.
+#include "col_wave.h"
 #include "conv_kernels.h"
 #include "launch.h"
 
 #include <stdlib.h>
+
+#include <type_traits>
 
 namespace bem {
 
@@ -15,9 +18,41 @@ int col_width_cap() {
   return cap;
 }
 
+int col_wave_enabled() {
+  static const int on = [] {
+    const char* v = getenv("BEM_COL_WAVE");
+    return v ? atoi(v) : 1;
+  }();
+  return on;
+}
+
+// Tuning knob: BEM_COL_NC = 2 or 4 columns per workgroup of the wave kernel.
+int col_wave_nc() {
+  static const int nc = [] {
+    const char* v = getenv("BEM_COL_NC");
+    return (v && atoi(v) == 2) ? 2 : 4;
+  }();
+  return nc;
+}
+
 template <typename T>
 hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int* done,
                       hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    // wave-FFT column kernel (Ly = 2048): NC columns per workgroup
+    if (col_wave_enabled() && g.Ly == 2048) {
+      if (col_wave_nc() == 2 && g.Lx % 2 == 0) {
+        hipLaunchKernelGGL((k_col_conv_w<2048, 2>), dim3(g.Lx / 2), dim3(256), 0, s, S, g.Lx, g.ny,
+                           K.KT, g.kpitch, K.twy, K.twly, done);
+        return hipGetLastError();
+      }
+      if (g.Lx % 4 == 0) {
+        hipLaunchKernelGGL((k_col_conv_w<2048, 4>), dim3(g.Lx / 4), dim3(512), 0, s, S, g.Lx, g.ny,
+                           K.KT, g.kpitch, K.twy, K.twly, done);
+        return hipGetLastError();
+      }
+    }
+  }
   const int W = col_width<T>(g.Ly, g.Lx);
   return dispatch_L(g.Ly, [&](auto LYc) -> hipError_t {
     constexpr int LY = decltype(LYc)::value;
@@ -41,9 +76,10 @@ hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cp
   hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    PlainLoad<T> pro{p, g.nx};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
-                       pro, S, g.nx, g.ny, K.twx);
+    constexpr int PER = row_per<L, NT>();
+    PlainLoad<T, PER> pro{p, g.nx};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT), 0,
+                       s, pro, S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -52,9 +88,10 @@ hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cp
   return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    PlainStore<T> epi{u, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
-                       S, g.nx, g.ny, K.twx, epi);
+    constexpr int PER = row_per<L, NT>();
+    PlainStore<T, PER> epi{u, g.nx};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
+                       0, s, S, g.nx, g.ny, K.twx, epi);
     return hipGetLastError();
   });
 }
@@ -66,14 +103,15 @@ hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T*
   return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
+    constexpr int PER = row_per<L, NT>();
     if (which == 0) {
-      PlainLoad<T> pro{p, g.nx};
-      hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
-                         pro, S, g.nx, g.ny, K.twx);
+      PlainLoad<T, PER> pro{p, g.nx};
+      hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
+                         0, s, pro, S, g.nx, g.ny, K.twx);
     } else {
-      PlainStore<T> epi{u, g.nx};
-      hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T>>), dim3((g.ny + 1) / 2), dim3(NT), 0,
-                         s, S, g.nx, g.ny, K.twx, epi);
+      PlainStore<T, PER> epi{u, g.nx};
+      hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
+                         0, s, S, g.nx, g.ny, K.twx, epi);
     }
     return hipGetLastError();
   });

@@ -36,48 +36,86 @@
 
 namespace bem {
 
-template <typename T>
+// Functor interface of the row sweeps.  Each thread handles the elements
+// n = threadIdx.x + q NTHR (q < PER) of the workgroup's two rows ya, yb.
+//  prologue (R2C): begin<NTHR>(red) -> false: the whole workgroup returns;
+//    load<NTHR>(ya, yb, hasb, nx, va, vb): all reads, values to transform
+//    (zero for n >= nx); commit<NTHR>(...): writes back updated state;
+//    finish<NTHR>(red): per-workgroup partial sums.
+//  epilogue (C2R): begin, prefetch<NTHR>(ya, yb, hasb, nx) (issued before
+//    the transform so the loads overlap it), consume<NTHR>(..., va, vb)
+//    with the convolution outputs, finish.
+template <typename T, int PER>
 struct PlainLoad {
   const T* in;
   int nx;
-  __device__ bool skip() const { return false; }
-  __device__ void begin() {}
-  __device__ T load(int y, int x) { return in[(size_t)y * nx + x]; }
+  template <int NTHR>
+  __device__ bool begin(double*) { return true; }
+  template <int NTHR>
+  __device__ void load(int ya, int yb, bool hasb, int nx_, T (&va)[PER], T (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      va[q] = n < nx_ ? in[(size_t)ya * nx + n] : T(0);
+      vb[q] = (n < nx_ && hasb) ? in[(size_t)yb * nx + n] : T(0);
+    }
+  }
+  template <int NTHR>
+  __device__ void commit(int, int, bool, int, const T (&)[PER], const T (&)[PER]) {}
   template <int NTHR>
   __device__ void finish(double*) {}
 };
 
-template <typename T>
+template <typename T, int PER>
 struct PlainStore {
   T* out;
   int nx;
-  __device__ bool skip() const { return false; }
-  __device__ void begin() {}
-  __device__ void store(int y, int x, T v) { out[(size_t)y * nx + x] = v; }
+  template <int NTHR>
+  __device__ bool begin(double*) { return true; }
+  template <int NTHR>
+  __device__ void prefetch(int, int, bool, int) {}
+  template <int NTHR>
+  __device__ void consume(int ya, int yb, bool hasb, int nx_, const T (&va)[PER],
+                          const T (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      if (n < nx_) {
+        out[(size_t)ya * nx + n] = va[q];
+        if (hasb) out[(size_t)yb * nx + n] = vb[q];
+      }
+    }
+  }
   template <int NTHR>
   __device__ void finish(double*) {}
 };
+
+template <int L, int NTHR>
+__host__ __device__ constexpr int row_per() { return (L + NTHR - 1) / NTHR; }
 
 template <typename T, int L, int NTHR, class Pro>
 __global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
                                                   int ny, const cplx<T>* __restrict__ tw) {
   constexpr int STR = lds_len(L);
+  constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
   Pro pro = pro_arg;
-  if (pro.skip()) return;
-  pro.begin();
+  if (!pro.template begin<NTHR>(red)) return;
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
-  for (int n = threadIdx.x; n < L; n += NTHR) {
-    cplx<T> z = {T(0), T(0)};
-    if (n < nx) {
-      z.x = pro.load(ya, n);
-      if (hasb) z.y = pro.load(yb, n);
+  T va[PER], vb[PER];
+  pro.template load<NTHR>(ya, yb, hasb, nx, va, vb);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int n = threadIdx.x + q * NTHR;
+    if (PER * NTHR == L || n < L) {
+      const cplx<T> z = {va[q], vb[q]};
+      lds[lds_pad(n)] = z;
+      lds[STR + lds_pad(n)] = cmul(z, tw[n]);
     }
-    lds[lds_pad(n)] = z;
-    lds[STR + lds_pad(n)] = cmul(z, tw[n]);
   }
+  pro.template commit<NTHR>(ya, yb, hasb, nx, va, vb);
   __syncthreads();
   fft_lds<T, L, -1, 2, NTHR, STR>(lds, tw);
   const cplx<T>* E = lds;
@@ -195,13 +233,14 @@ template <typename T, int L, int NTHR, class Epi>
 __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
                                                   const cplx<T>* __restrict__ tw, Epi epi_arg) {
   constexpr int STR = lds_len(L);
+  constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
   Epi epi = epi_arg;
-  if (epi.skip()) return;
-  epi.begin();
+  if (!epi.template begin<NTHR>(red)) return;
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
+  epi.template prefetch<NTHR>(ya, yb, hasb, nx);
   const cplx<T>* Sa = S + (size_t)ya * L;
   const cplx<T>* Sb = S + (size_t)yb * L;
   for (int k = threadIdx.x; k < L; k += NTHR) {
@@ -220,11 +259,16 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
   }
   __syncthreads();
   fft_lds<T, L, +1, 2, NTHR, STR>(lds, tw);
-  for (int n = threadIdx.x; n < nx; n += NTHR) {
-    const cplx<T> z = cadd(lds[lds_pad(n)], cmulc(lds[STR + lds_pad(n)], tw[n]));
-    epi.store(ya, n, z.x);
-    if (hasb) epi.store(yb, n, z.y);
+  T va[PER], vb[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int n = threadIdx.x + q * NTHR;
+    cplx<T> z = {T(0), T(0)};
+    if (n < nx) z = cadd(lds[lds_pad(n)], cmulc(lds[STR + lds_pad(n)], tw[n]));
+    va[q] = z.x;
+    vb[q] = z.y;
   }
+  epi.template consume<NTHR>(ya, yb, hasb, nx, va, vb);
   epi.template finish<NTHR>(red);
 }
 

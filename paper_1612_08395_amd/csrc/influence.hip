@@ -135,24 +135,47 @@ __global__ void k_twiddles(cplx<double>* __restrict__ t64, cplx<float>* __restri
   t32[m] = {(float)c, (float)-s};
 }
 
+__global__ void k_wave_twiddles(cplx<double>* __restrict__ t64, cplx<float>* __restrict__ t32,
+                                int L) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;   // m = k1 * 64 + l
+  if (m >= L) return;
+  const int k1 = m >> 6, l = m & 63;
+  double s, c;
+  sincospi(2.0 * (double)(l * k1) / (double)L, &s, &c);
+  t64[m] = {c, -s};
+  t32[m] = {(float)c, (float)-s};
+}
+
 // Q(i, j) = K(i, j) c_i c_j (see file header)
+template <int PER>
 struct QLoad {
   const double* Kq;
   int nx;
-  __device__ bool skip() const { return false; }
-  __device__ void begin() {}
-  __device__ double load(int y, int x) {
-    double v = Kq[(size_t)y * nx + x];
-    if (x == 0) v *= 0.5;
-    if (y == 0) v *= 0.5;
-    return v;
+  template <int NTHR>
+  __device__ bool begin(double*) { return true; }
+  template <int NTHR>
+  __device__ void load(int ya, int yb, bool hasb, int nxl, double (&va)[PER], double (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const double cx = n == 0 ? 0.5 : 1.0;
+      va[q] = n < nxl ? Kq[(size_t)ya * nx + n] * cx * (ya == 0 ? 0.5 : 1.0) : 0.0;
+      vb[q] = (n < nxl && hasb) ? Kq[(size_t)yb * nx + n] * cx : 0.0;
+    }
   }
+  template <int NTHR>
+  __device__ void commit(int, int, bool, int, const double (&)[PER], const double (&)[PER]) {}
   template <int NTHR>
   __device__ void finish(double*) {}
 };
 
 hipError_t launch_twiddles(cplx<double>* t64, cplx<float>* t32, int M, hipStream_t s) {
   hipLaunchKernelGGL(k_twiddles, dim3((M + 255) / 256), dim3(256), 0, s, t64, t32, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave_twiddles(cplx<double>* t64, cplx<float>* t32, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_wave_twiddles, dim3((L + 255) / 256), dim3(256), 0, s, t64, t32, L);
   return hipGetLastError();
 }
 
@@ -172,9 +195,10 @@ hipError_t launch_spectrum(const Geom& g, const double* Kq, cplx<double>* S,
   hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
-    QLoad q{Kq, g.nx};
-    hipLaunchKernelGGL((k_row_r2c<double, L, NT, QLoad>), dim3((g.ny + 1) / 2), dim3(NT), 0, s, q,
-                       S, g.nx, g.ny, twx);
+    constexpr int PER = row_per<L, NT>();
+    QLoad<PER> q{Kq, g.nx};
+    hipLaunchKernelGGL((k_row_r2c<double, L, NT, QLoad<PER>>), dim3((g.ny + 1) / 2), dim3(NT), 0, s,
+                       q, S, g.nx, g.ny, twx);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;

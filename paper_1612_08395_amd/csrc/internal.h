@@ -21,6 +21,8 @@ struct bem_influence_s {
   bem::cplx<double>* twy64 = nullptr;
   bem::cplx<float>* twx32 = nullptr;
   bem::cplx<float>* twy32 = nullptr;
+  bem::cplx<double>* twly64 = nullptr;  // wave-FFT table for length Ly (Ly = 64 P)
+  bem::cplx<float>* twly32 = nullptr;
   // lazily allocated scratch of the convolution entry points
   bem::cplx<double>* S64 = nullptr;
   bem::cplx<float>* S32 = nullptr;

@@ -21,6 +21,7 @@ struct SpecView {
   const T* KT;             // (Lx + 1) x kpitch, pre-scaled by C / (Mx My)
   const cplx<T>* twx;      // Mx-point twiddles
   const cplx<T>* twy;      // My-point twiddles
+  const cplx<T>* twly;     // wave-FFT inter-step table [k1][lane] for length Ly (or null)
 };
 
 // Workgroup sizes and column-group widths, shared by launchers and the
@@ -87,6 +88,8 @@ inline hipError_t dispatch_W(int W, F&& f) {
 }
 
 hipError_t launch_twiddles(cplx<double>* t64, cplx<float>* t32, int M, hipStream_t s);
+// wave-FFT table for length L = 64 P: t[k1 * 64 + l] = exp(-2 pi i l k1 / L)
+hipError_t launch_wave_twiddles(cplx<double>* t64, cplx<float>* t32, int L, hipStream_t s);
 hipError_t launch_influence(double* Kq, int nx, int ny, double dx, double dy, double k,
                             hipStream_t s);
 hipError_t launch_spectrum(const Geom& g, const double* Kq, cplx<double>* S,

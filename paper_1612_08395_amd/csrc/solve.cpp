@@ -36,11 +36,12 @@ struct bem_state_s {
   CgScal* sc_host = nullptr;  // pinned
   bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
   long long device_bytes = 0;
+  int last_iters[2] = {0, 0};  // iterations of the previous CG solve, per mode
 };
 
 namespace {
 
-constexpr int kPartials = 8192;
+constexpr int kPartials = kPartTotal;
 
 int salloc(bem_state_s* st, void** p, size_t bytes, const char* what) {
   hipError_t e = hipMalloc(p, bytes);
@@ -116,10 +117,7 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
            hipStream_t s) {
   CgScal* h = st->sc_host;
   std::memset(h, 0, sizeof(CgScal));
-  h->G_old = 1.0;
-  h->best_G = 1e300;
   h->tol = cfg.tol;
-  h->first = 1;
   h->max_iter = cfg.max_iter;
   h->stall_limit = cfg.stall_limit;
   hipError_t e = hipMemcpyAsync(st->sc, h, sizeof(CgScal), hipMemcpyHostToDevice, s);
@@ -130,22 +128,27 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
   const Geom& g = st->K->g;
   const SpecView<T> K = spec_view<T>(st->K);
   const CgBufs<T> b = bufs<T>(st);
-  int chunk = 4;
-  long long queued = 0;
+  // First chunk sized from the previous solve of this state (warm-started
+  // sweeps converge in similar counts), then small doubling chunks.
+  int& last = st->last_iters[fixed_set ? 1 : 0];
+  int chunk = last > 0 ? std::min(std::max(last + 2, 4), 64) : 4;
+  int next = 4;
+  int it = 0;
   for (;;) {
-    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, chunk, s)) != hipSuccess)
+    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, it, chunk, s)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
-    queued += chunk;
+    it += chunk;
     if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
       return hip_fail(e, "solver scalars");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "CG iteration");
     if (h->done) break;
     // the device stops itself at max_iter; this only guards the host loop
-    if (queued > (long long)cfg.max_iter + 256)
-      return set_error(BEM_EDEVICE, "CG loop did not report completion");
-    chunk = std::min(chunk * 2, 32);
+    if (it > cfg.max_iter + 256) return set_error(BEM_EDEVICE, "CG loop did not report completion");
+    chunk = next;
+    next = std::min(next * 2, 32);
   }
   *iters = h->iter;
+  last = h->iter;
   *resid = h->rhs2 > 0 ? std::sqrt(h->G / h->rhs2) : std::sqrt(h->G);
   return status_code(h->status);
 }
@@ -449,6 +452,7 @@ int bem_state_reset(bem_state_t st) {
   clear_error();
   if (!st) return set_error(BEM_EINVAL, "bem_state_reset: NULL state");
   st->has_p = st->has_mask = st->pending_import = st->import_mask = false;
+  st->last_iters[0] = st->last_iters[1] = 0;
   return BEM_OK;
 }
 

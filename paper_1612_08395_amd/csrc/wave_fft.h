@@ -1,0 +1,207 @@
+// Wave-level FFT of length L = 64 P (P = 32 or 64) for the column sweep of
+// Eq. 13: one wave64 owns one sequence, P points per lane, with a single
+// LDS transpose per direction.
+//
+// With n = l + 64 m (lane l, register m) and k = k1 + P k2:
+//   forward  A[l][k1] = sum_m x[l + 64 m] w_P^(m k1)          (registers)
+//            B[l][k1] = A[l][k1] w_L^(l k1)                     (twiddle)
+//            X[k1 + P k2] = sum_l B[l][k1] w_64^(l k2)          (after transpose)
+// The 64-point transform over l runs in registers after the transpose: for
+// P = 64 each lane owns one k1 and all 64 values of l; for P = 32 two lanes
+// share a k1, each owning half of l (l = 2i + h), and a radix-2 step
+// between the two lanes (DPP quad permutation) finishes it.  The output
+// stays in this permuted order: lane (k1, h), register k2 holds frequency
+// f = k1 + 32 (k2 + 32 h) (P = 32) or f = k1 + 64 k2 (P = 64).  The
+// spectrum multiplication does not care about order, and the inverse runs
+// the transposed algorithm (same stages in reverse, conjugate twiddles), so
+// it reads the permuted order and returns y[l + 64 m] in natural order.
+//
+// Register DFTs use constant twiddles (cosines of pi t / 64, exact quadrant
+// symmetry); the inter-step twiddle w_L^(l k1) comes from a per-length table
+// laid out [k1][lane], each entry rounded once from FP64.
+#pragma once
+#include "common.h"
+#include "fft_lds.h"
+
+namespace bem {
+
+// cos(pi t / 64), t = 0..32
+__host__ __device__ constexpr double cos_q(int t) {
+  constexpr double c[33] = {
+      1.0, 0.9987954562051724, 0.9951847266721969, 0.989176509964781,
+      0.9807852804032304, 0.970031253194544, 0.9569403357322088, 0.9415440651830208,
+      0.9238795325112867, 0.9039892931234433, 0.881921264348355, 0.8577286100002721,
+      0.8314696123025452, 0.8032075314806449, 0.773010453362737, 0.7409511253549591,
+      0.7071067811865476, 0.6715589548470183, 0.6343932841636455, 0.5956993044924335,
+      0.5555702330196023, 0.5141027441932217, 0.4713967368259978, 0.4275550934302822,
+      0.38268343236508984, 0.33688985339222005, 0.29028467725446233, 0.24298017990326398,
+      0.19509032201612833, 0.14673047445536175, 0.09801714032956077, 0.049067674327418126,
+      0.0};
+  return c[t];
+}
+
+// cos / sin of 2 pi t / 128 for any integer t, from the quadrant table
+__host__ __device__ constexpr double cos128(int t) {
+  t &= 127;
+  return t <= 32 ? cos_q(t) : t <= 64 ? -cos_q(64 - t) : t <= 96 ? -cos_q(t - 64) : cos_q(128 - t);
+}
+__host__ __device__ constexpr double sin128(int t) { return cos128(t - 32); }
+
+__host__ __device__ constexpr int bitrev(int i, int n) {
+  int r = 0;
+  for (int b = 1; b < n; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// y * w_N^j with w_N = exp(DIR 2 pi i / N), N <= 128, N | 128
+template <typename T, int DIR>
+__device__ __forceinline__ cplx<T> mul_wn(cplx<T> y, int j, int N) {
+  const int t = (j * (128 / N)) & 127;
+  if (t == 0) return y;
+  if (t == 64) return {-y.x, -y.y};
+  if (t == 32) return rot90<DIR>(y);
+  if (t == 96) return rot90<-DIR>(y);
+  const T c = (T)cos128(t), s = (T)(DIR * sin128(t));
+  return {y.x * c - y.y * s, y.x * s + y.y * c};
+}
+
+// In-register DFT of P points, natural order in and out (radix-2 DIT on a
+// compile-time bit-reversed copy; every index is a constant after unrolling).
+template <typename T, int P, int DIR>
+__device__ __forceinline__ void reg_dft(cplx<T> (&v)[P]) {
+  cplx<T> a[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) a[i] = v[bitrev(i, P)];
+#pragma unroll
+  for (int s = 1; s < P; s <<= 1) {
+#pragma unroll
+    for (int b = 0; b < P; b += 2 * s) {
+#pragma unroll
+      for (int j = 0; j < s; ++j) {
+        const cplx<T> x = a[b + j];
+        const cplx<T> y = mul_wn<T, DIR>(a[b + j + s], j, 2 * s);
+        a[b + j] = cadd(x, y);
+        a[b + j + s] = csub(x, y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = a[i];
+}
+
+// v[k1] *= w_L^(lane k1) (DIR = -1) or its conjugate (DIR = +1).  twl is a
+// table laid out [k1][lane]: twl[k1 * 64 + l] = exp(-2 pi i l k1 / L), each
+// entry computed in FP64 and rounded once (coalesced across the wave).
+template <typename T, int P, int DIR>
+__device__ __forceinline__ void twiddle_lk1(cplx<T> (&v)[P], const cplx<T>* __restrict__ twl,
+                                            int lane) {
+#pragma unroll
+  for (int k1 = 1; k1 < P; ++k1) {
+    const cplx<T> w = twl[k1 * 64 + lane];
+    v[k1] = (DIR < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
+  }
+}
+
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_xor1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// LDS words per wave region (complex elements): P rows of 64 + 1 padding
+template <int P>
+__host__ __device__ constexpr int wave_region() { return P * 65; }
+
+// The transpose regions are private to a wave, so a wave-level ordering
+// point suffices between writing a region and reading other lanes' values:
+// LDS instructions of one wave execute in order, and the fences stop the
+// compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Frequency index held by (lane, register r) after the forward transform.
+template <int P>
+__device__ __forceinline__ int wave_freq(int lane, int r) {
+  if constexpr (P == 32) return (lane >> 1) + 32 * r + 1024 * (lane & 1);
+  else return lane + 64 * r;
+}
+
+// Forward transform.  `reg` is this wave's private LDS region (P * 65).
+template <typename T, int P>
+__device__ __forceinline__ void wave_fft_fwd(cplx<T> (&v)[P], cplx<T>* reg,
+                                             const cplx<T>* __restrict__ twl, int lane) {
+  static_assert(P == 32 || P == 64, "wave FFT sizes");
+  reg_dft<T, P, -1>(v);
+  twiddle_lk1<T, P, -1>(v, twl, lane);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) reg[k1 * 65 + lane] = v[k1];
+  wave_lds_sync();
+  if constexpr (P == 32) {
+    const int k1 = lane >> 1, h = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = reg[k1 * 65 + 2 * i + h];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) v[i] = reg[lane * 65 + i];
+  }
+  wave_lds_sync();
+  reg_dft<T, P, -1>(v);
+  if constexpr (P == 32) {
+    // lane pair (h = 0: E, h = 1: O): X_lo = E + w O, X_hi = E - w O
+    const bool hi = lane & 1;
+    const T sg = hi ? T(-1) : T(1);
+#pragma unroll
+    for (int k2 = 0; k2 < 32; ++k2) {
+      const cplx<T> o = {lane_xor1(v[k2].x), lane_xor1(v[k2].y)};
+      const cplx<T> e = hi ? o : v[k2];
+      const cplx<T> wo = mul_wn<T, -1>(hi ? v[k2] : o, k2, 64);
+      v[k2] = {e.x + sg * wo.x, e.y + sg * wo.y};
+    }
+  }
+}
+
+// Inverse (unnormalised) transform from the permuted frequency layout back
+// to y[lane + 64 m] in v[m].
+template <typename T, int P>
+__device__ __forceinline__ void wave_fft_inv(cplx<T> (&v)[P], cplx<T>* reg,
+                                             const cplx<T>* __restrict__ twl, int lane) {
+  if constexpr (P == 32) {
+    // h = 0 keeps X_lo + X_hi, h = 1 keeps (X_lo - X_hi) w^(-k2)
+    const bool hi = lane & 1;
+    const T sg = hi ? T(-1) : T(1);
+#pragma unroll
+    for (int k2 = 0; k2 < 32; ++k2) {
+      const cplx<T> o = {lane_xor1(v[k2].x), lane_xor1(v[k2].y)};
+      const cplx<T> sum = {o.x + sg * v[k2].x, o.y + sg * v[k2].y};
+      const cplx<T> tw = mul_wn<T, +1>(sum, k2, 64);
+      v[k2] = hi ? tw : sum;
+    }
+  }
+  reg_dft<T, P, +1>(v);
+  if constexpr (P == 32) {
+    const int k1 = lane >> 1, h = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) reg[k1 * 65 + 2 * i + h] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) reg[lane * 65 + i] = v[i];
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) v[k1] = reg[k1 * 65 + lane];
+  wave_lds_sync();
+  twiddle_lk1<T, P, +1>(v, twl, lane);
+  reg_dft<T, P, +1>(v);
+}
+
+}  // namespace bem
