@@ -17,7 +17,6 @@ pressure error per depth, the roofline of the dominant kernel and the FP64
 CPU oracle timed on the host cores (bounded sample).
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -88,9 +87,15 @@ def run_sweep(bem, K, h_dev, depths, precision, keep_p=False, torch=None):
 
 
 def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
+    """Times `steps` sweeps.  The library's solver clock runs over the timed
+    region (HIP events on the solver stream around every CG launch); warmup
+    runs it too, so the per-thread event pool is already grown."""
+    bem.bem_clock_start()
     for _ in range(warmup):
         run_sweep(bem, K, h_dev, depths, precision)
     torch.cuda.synchronize()
+    bem.bem_clock_stop()
+    bem.bem_clock_start()
     t0 = time.perf_counter()
     results = []
     for _ in range(steps):
@@ -98,43 +103,47 @@ def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
         results.append(r)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0), results
+    clock = bem.bem_clock_stop()
+    return (t1 - t0), results, clock
 
 
-def kernel_source_sha():
-    h = hashlib.sha256()
-    for f in ("conv_kernels.h", "fft_lds.h", "wave_fft.h", "col_wave.h", "common.h", "launch.h",
-              "conv.hip"):
-        with open(os.path.join(HERE, "paper_1612_08395_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def roofline(bem, K, torch):
-    """Dominant kernel: the fused column sweep (FFT x spectrum x IFFT), FP32.
-    Algorithmic bytes per launch: read + write the ny x Lx complex row
-    spectrum and read the (Lx+1) x (Ly+1) real kernel spectrum."""
+def roofline(bem, K, clock, torch):
+    """Dominant kernel: the fused column sweep (FFT x spectrum x IFFT), FP32,
+    launched twice per CG iteration.  Algorithmic bytes per launch: read +
+    write the ny x Lx complex row spectrum and read the (Lx+1) x (Ly+1) real
+    kernel spectrum.  Duration: the solver clock's mean over every column
+    launch of the timed sweeps that did work (HIP events on the solver
+    stream)."""
     info = K.info
     Lx, Ly = info.Mx // 2, info.My // 2
     bytes_per_launch = 2 * info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
-    stream = torch.cuda.current_stream()
-    ms = bem.bem_kernel_time(K, bem.BEM_MIXED, 1, reps=50, stream=stream)
+    n_col = clock.launches[1] + clock.launches[4]
+    ms = (clock.ms[1] + clock.ms[4]) / n_col
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
+        from paper_1612_08395_amd.profile_summary import kernel_source_sha
         if tr.get("source_sha") == kernel_source_sha():
             traffic = tr.get("bytes_per_launch")
-    other = {}
-    for which, name in ((0, "row_r2c"), (2, "row_c2r")):
-        t = bem.bem_kernel_time(K, bem.BEM_MIXED, which, reps=50, stream=stream)
-        b = info.ny * info.nx * 4 + info.ny * Lx * 8
-        other[name] = {"ms": round(t, 5), "GB/s": round(b / (t * 1e-3) / 1e9, 1)}
-    return {"bound": "hbm", "kernel": "k_col_conv<float,2048,4,512>", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "ms_per_launch": round(ms, 5),
-            "algorithmic_bytes_per_launch": bytes_per_launch, "other_sweeps": other}
+    stream = torch.cuda.current_stream()
+    iso = bem.bem_kernel_time(K, bem.BEM_MIXED, 1, reps=50, stream=stream)
+    loop = {name: round(clock.ms[k] / max(1, clock.launches[k]) * 1e3, 2)
+            for k, name in enumerate(("update_r2c", "column_1", "gap_c2r", "direction_r2c",
+                                      "column_2", "dots_c2r"))}
+    return {"bound": "hbm", "kernel": "k_col_conv_w<2048,4> (column sweep, FP32)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "ms_per_launch": round(ms, 5), "launches_timed": n_col,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "timing": "HIP events on the solver stream around each column launch of the "
+                      "timed sweeps, launches past convergence excluded",
+            "isolated_ms_per_launch": round(iso, 5),
+            "loop_us_per_launch": loop,
+            "loop_us_per_iteration": round(sum(clock.ms) / clock.iterations * 1e3, 2),
+            "skipped_launches": clock.skipped,
+            "skipped_us_total": round(clock.skipped_ms * 1e3, 1)}
 
 
 def cpu_baseline(h, depths, iters_per_solve, sample_iters):
@@ -144,7 +153,9 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
     from oracle import material as m
     from oracle import solver as so
     from oracle.convolution import FFTConvolver
-    cores = os.cpu_count() or 1
+    # worker threads: the CPUs this process may use, capped by OMP_NUM_THREADS
+    cores = len(os.sched_getaffinity(0))
+    cores = max(1, min(cores, int(os.environ.get("OMP_NUM_THREADS", cores))))
     dx = L / N
     t_setup = time.perf_counter()
     Kq = inf.influence_quarter(N, N, dx, dx, K_EXP)
@@ -191,14 +202,18 @@ def serving(count, slots, bem):
 
 
 def profile_kernels(bem, torch):
-    """Few launches of each sweep kernel at 2048^2 (for rocprofv3 --pmc) and a
-    plain device copy of 2^28 floats (1 GiB read + 1 GiB written) whose
-    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    """Few launches of each sweep kernel at 2048^2 (for rocprofv3 --pmc), one
+    mixed-precision solve of the bench workload at the deepest depth (the
+    fused CG kernels), and a plain device copy of 2^28 floats (1 GiB read +
+    1 GiB written) whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
     K = bem.bem_influence(N, N, L / N, K_EXP, NU)
     out = {}
     for prec, name in ((bem.BEM_MIXED, "f32"), (bem.BEM_FP64, "f64")):
         for which, kname in ((0, "row_r2c"), (1, "col_conv"), (2, "row_c2r")):
             out[f"{kname}_{name}_ms"] = bem.bem_kernel_time(K, prec, which, reps=4)
+    h_dev = torch.tensor(workload(), dtype=torch.float64, device="cuda")
+    _, res = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=D10, precision=bem.BEM_MIXED))
+    out["solve_iters"] = res.iters
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -258,9 +273,10 @@ def main():
     del p64, p32
 
     log("[bench] timed mixed sweeps")
-    t32, res32 = timed(bem, K, h_dev, depths, bem.BEM_MIXED, args.steps, args.warmup, torch)
+    t32, res32, clk32 = timed(bem, K, h_dev, depths, bem.BEM_MIXED, args.steps, args.warmup,
+                              torch)
     log("[bench] timed FP64 sweeps")
-    t64, res64 = timed(bem, K, h_dev, depths, bem.BEM_FP64, args.fp64_steps, 0, torch)
+    t64, res64, clk64 = timed(bem, K, h_dev, depths, bem.BEM_FP64, args.fp64_steps, 0, torch)
     it32 = [x["iters"] for x in res32[-1]]
     it64 = [x["iters"] for x in res64[-1]]
     solves32 = N_DEPTHS * args.steps / t32
@@ -272,7 +288,7 @@ def main():
     loop64 = 248.0 * N * N * sum(it64) / (t64 / args.fp64_steps) / 1e9
 
     log("[bench] roofline")
-    roof = roofline(bem, K, torch)
+    roof = roofline(bem, K, clk32, torch)
     out = {
         "metric": METRIC, "value": round(solves32, 3), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -287,7 +303,9 @@ def main():
         "fp64": {"value": round(solves64, 3), "unit": "solves/s", "steps": args.fp64_steps,
                  "ms_per_step": round(t64 / args.fp64_steps * 1e3, 3),
                  "iters_per_solve": round(sum(it64) / len(it64), 2),
-                 "loop_GBps_algorithmic": round(loop64, 1)},
+                 "loop_GBps_algorithmic": round(loop64, 1),
+                 "column_us_per_launch": round((clk64.ms[1] + clk64.ms[4]) /
+                                               (clk64.launches[1] + clk64.launches[4]) * 1e3, 2)},
         "iters_per_solve": round(sum(it32) / len(it32), 2),
         "loop_GBps_algorithmic": round(loop32, 1),
         "mixed_vs_fp64": {"rel_l2_pressure_per_depth": [float(f"{e:.3e}") for e in err],

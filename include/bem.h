@@ -289,6 +289,34 @@ int bem_server_free(bem_server_t srv);
 int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void* stream,
                     double* avg_ms);
 
+/*
+ * Solver clock -- measurement hook for the conjugate-gradient loop of the
+ * contact solve (Section 2.2, Polonsky-Keer iteration; each iteration is two
+ * convolutions of Eq. 13, i.e. six kernel launches:
+ *   0 pressure update + row R2C,  1 column sweep,  2 row C2R + gap,
+ *   3 direction + row R2C,        4 column sweep,  5 row C2R + dot products).
+ * After bem_clock_start, every bem_solve / bem_solve_dev / bem_sweep made BY
+ * THE CALLING THREAD records a HIP event on its solver stream before the
+ * first launch of each queued chunk and after every launch; no extra host
+ * synchronisation is added.  bem_clock_stop resolves the events and returns,
+ * per launch kind, the number of launches and their summed event-to-event
+ * durations, counting only iterations the solver actually worked on; the
+ * launches queued past convergence (which return at once) are summed
+ * separately.  Durations include the command processor's dispatch gap
+ * between back-to-back launches (about a microsecond).  Not for server
+ * worker threads.  bem_clock_stop on a thread without a running clock
+ * returns BEM_EINVAL.
+ */
+typedef struct {
+  long long iterations;    /* CG iterations worked on */
+  long long launches[6];   /* launches per kind that did work */
+  double ms[6];            /* their summed durations (ms) */
+  long long skipped;       /* launches queued past convergence */
+  double skipped_ms;       /* their summed durations (ms) */
+} bem_clock_t;
+int bem_clock_start(void);
+int bem_clock_stop(bem_clock_t* out);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* bem_last_error(void);
 

@@ -330,6 +330,34 @@ def bem_kernel_time(K, precision, which, reps=20, stream=None):
     return ms.value
 
 
+class Clock(ctypes.Structure):
+    """Per-launch-kind totals of the solver clock; kinds in CG-iteration order:
+    update+R2C, column, C2R+gap, direction+R2C, column, C2R+dots."""
+    _fields_ = [("iterations", ctypes.c_longlong), ("launches", ctypes.c_longlong * 6),
+                ("ms", _c_double * 6), ("skipped", ctypes.c_longlong),
+                ("skipped_ms", _c_double)]
+
+    KINDS = ("update_r2c", "column", "gap_c2r", "direction_r2c", "column", "dots_c2r")
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "launches": list(self.launches),
+                "ms": list(self.ms), "skipped": self.skipped, "skipped_ms": self.skipped_ms}
+
+
+_f_clock_start = _sig("bem_clock_start", _c_int, [])
+_f_clock_stop = _sig("bem_clock_stop", _c_int, [ctypes.POINTER(Clock)])
+
+
+def bem_clock_start():
+    _check(_f_clock_start())
+
+
+def bem_clock_stop():
+    c = Clock()
+    _check(_f_clock_stop(ctypes.byref(c)))
+    return c
+
+
 # ---- serving -----------------------------------------------------------------
 
 class Request(ctypes.Structure):

@@ -24,9 +24,14 @@ inline int ew_blocks(size_t n) {
   return (int)(b > EW_MAX_BLOCKS ? EW_MAX_BLOCKS : b);
 }
 
+// ev (optional): six events recorded after the six launches, in order.
+inline hipError_t mark(const hipEvent_t* ev, int k, hipStream_t s) {
+  return ev ? hipEventRecord(ev[k], s) : hipSuccess;
+}
+
 template <typename T, bool FS>
 hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int it,
-                               hipStream_t s) {
+                               const hipEvent_t* ev, hipStream_t s) {
   const int nrp = (g.ny + 1) / 2;
   hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
@@ -37,8 +42,9 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
                        b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || (e = mark(ev, 0, s)) != hipSuccess) return e;
   if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
+  if ((e = mark(ev, 1, s)) != hipSuccess) return e;
   e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
@@ -48,7 +54,7 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
                        g.nx, g.ny, K.twx, ge);
     return hipGetLastError();
   });
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || (e = mark(ev, 2, s)) != hipSuccess) return e;
   e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
@@ -58,9 +64,10 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
                        b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || (e = mark(ev, 3, s)) != hipSuccess) return e;
   if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
-  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+  if ((e = mark(ev, 4, s)) != hipSuccess) return e;
+  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
@@ -69,15 +76,22 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
                        g.nx, g.ny, K.twx, de);
     return hipGetLastError();
   });
+  if (e != hipSuccess) return e;
+  return mark(ev, 5, s);
 }
 
-// Queue iterations it0 .. it0 + n - 1.
+// Queue iterations it0 .. it0 + n - 1.  ev (optional): 6 n + 1 events, the
+// first recorded before the first launch, then six per iteration.
 template <typename T>
 hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
-                                bool fixed_set, int it0, int n, hipStream_t s) {
+                                bool fixed_set, int it0, int n, const hipEvent_t* ev,
+                                hipStream_t s) {
+  hipError_t e = mark(ev, 0, s);
+  if (e != hipSuccess) return e;
   for (int i = 0; i < n; ++i) {
-    hipError_t e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, it0 + i, s)
-                             : launch_cg_iteration<T, false>(g, K, b, it0 + i, s);
+    const hipEvent_t* evi = ev ? ev + 1 + 6 * i : nullptr;
+    e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, it0 + i, evi, s)
+                  : launch_cg_iteration<T, false>(g, K, b, it0 + i, evi, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -142,7 +156,7 @@ hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, s
 
 #define BEM_INSTANTIATE_CG(T)                                                                    \
   template hipError_t launch_cg_iterations<T>(const Geom&, const SpecView<T>&, const CgBufs<T>&, \
-                                              bool, int, int, hipStream_t);                      \
+                                              bool, int, int, const hipEvent_t*, hipStream_t);   \
   template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \
   template hipError_t launch_cold_start<T>(T*, const T*, double, size_t, hipStream_t);           \
   template hipError_t launch_prepare<T>(T*, T*, const uint8_t*, bool, size_t, hipStream_t);      \

@@ -35,6 +35,12 @@ namespace bem {
 int set_error(int code, const char* fmt, ...);
 void clear_error();
 int hip_fail(hipError_t e, const char* what);
+
+// Solver clock (clock.cpp): events for a chunk of n CG iterations starting at
+// it0 (nullptr when the calling thread's clock is off), and the outcome of
+// that chunk once the host has synchronised.
+const hipEvent_t* clock_chunk(int it0, int n);
+void clock_chunk_done(bool done, int final_it);
 double alpha_kn(double k, double nu);
 bool is_finite(double v);
 

@@ -135,12 +135,14 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
   int next = 4;
   int it = 0;
   for (;;) {
-    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, it, chunk, s)) != hipSuccess)
+    const hipEvent_t* ev = clock_chunk(it, chunk);
+    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, it, chunk, ev, s)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
     it += chunk;
     if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
       return hip_fail(e, "solver scalars");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "CG iteration");
+    clock_chunk_done(h->done != 0, h->iter);
     if (h->done) break;
     // the device stops itself at max_iter; this only guards the host loop
     if (it > cfg.max_iter + 256) return set_error(BEM_EDEVICE, "CG loop did not report completion");

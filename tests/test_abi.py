@@ -54,3 +54,13 @@ def test_oversized_grid_unsupported():
     with pytest.raises(bem.BemError) as e:
         bem.bem_influence(bem.BEM_MAX_N + 1, 8, 0.1, 0.3, 0.3)
     assert e.value.code == bem.BEM_EUNSUPPORTED
+
+
+def test_solver_clock_host_paths():
+    from paper_1612_08395_amd import bem
+    with pytest.raises(bem.BemError) as e:         # no clock running on this thread
+        bem.bem_clock_stop()
+    assert e.value.code == bem.BEM_EINVAL
+    bem.bem_clock_start()
+    c = bem.bem_clock_stop()                       # no solve in between: nothing timed
+    assert c.iterations == 0 and c.skipped == 0 and list(c.launches) == [0] * 6

@@ -177,6 +177,29 @@ def test_adhesive_step_transitions_parity():
     K.free()
 
 
+def test_solver_clock_accounts_every_launch():
+    """The solver clock sees six launches per CG iteration: all six for the
+    iterations worked on, the first three at the stopping iteration (the
+    direction kernel there only takes the decision), and every launch queued
+    after it as skipped."""
+    bem = _bem()
+    announce("solver-clock")
+    n = 64
+    K = bem.bem_influence(n, n, 1.0 / n, 0.3, 0.3)
+    h = inputs.parabolic(n, 1.0, 1.0)
+    total = 0
+    bem.bem_clock_start()
+    for d in (0.002, 0.004):
+        _, res, _, _, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, precision=bem.BEM_MIXED))
+        total += res.iters
+    c = bem.bem_clock_stop()
+    K.free()
+    assert c.iterations == total
+    assert list(c.launches) == [total + 2] * 3 + [total] * 3
+    assert c.skipped % 6 == 0 and c.skipped >= 6   # two solves, three skipped at each stop
+    assert all(x > 0 for x in c.ms)
+
+
 def test_error_paths():
     bem = _bem()
     announce("errors")
