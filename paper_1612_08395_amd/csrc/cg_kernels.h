@@ -112,6 +112,39 @@ __device__ __forceinline__ void read_totals(const double* __restrict__ part, int
   block_sum_n<NV, NTHR>(tot, red);
 }
 
+// read_totals split in two: issue() loads this thread's first R partials
+// into registers (before the caller issues its field loads, so that waiting
+// for them does not wait for the fields), total() adds them, and any beyond
+// R NTHR, in the same order as read_totals.
+template <int NV>
+struct Partials {
+  static constexpr int R = 4;
+  double v[R][NV];
+  template <int NTHR>
+  __device__ __forceinline__ void issue(const double* __restrict__ part, int nb) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * NTHR;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[r][k] = load_or0(part, (size_t)i * NV + k, 0, i < nb);
+    }
+  }
+  template <int NTHR>
+  __device__ __forceinline__ void total(const double* __restrict__ part, int nb, double* red,
+                                        double (&tot)[NV]) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tot[k] += v[r][k];
+    for (int i = threadIdx.x + R * NTHR; i < nb; i += NTHR)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tot[k] += part[i * NV + k];
+    block_sum_n<NV, NTHR>(tot, red);
+  }
+};
+
 // Last-workgroup reduction, used only by the once-per-solve elementwise
 // kernels (agent-scope stores, fence, ticket).
 template <int NV, int NTHR>
@@ -157,16 +190,47 @@ struct UpdatePro {
   double* part;
   int nx, nb, it;
   double tau, a_dp, a_p, a_ol;
+  T pa[PER], pb[PER], ta[PER], tb[PER], ga[PER], gb[PER];
+  bool ma[PER], mb[PER];
+  Partials<2> dots;
   template <int NTHR>
-  __device__ bool begin(double* red) {
+  __device__ bool issue() {
     if (sc->done) return false;
-    a_dp = a_p = a_ol = 0.0;
-    tau = 0.0;
-    if (it > 0) {
-      double tot[2];
-      read_totals<2, NTHR>(part + kPartDots, nb, red, tot);
-      tau = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
+    // always issued (a valid buffer; unused when it == 0) so that no branch
+    // separates these loads from the field loads
+    dots.template issue<NTHR>(part + kPartDots, nb);
+    return true;
+  }
+  template <int NTHR>
+  __device__ void fetch(int ya, int yb, bool hasb, int nxl) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t ia = (size_t)ya * nx + n, ib = (size_t)yb * nx + n, sf = (size_t)ya * nx;
+      pa[q] = load_or0(p, ia, sf, in);
+      pb[q] = load_or0(p, ib, sf, inb);
+      // t, g (mask) are only used when it > 0; loading them unconditionally
+      // keeps every load of the thread in flight together
+      ta[q] = load_or0(t, ia, sf, in);
+      tb[q] = load_or0(t, ib, sf, inb);
+      ga[q] = gb[q] = T(0);
+      ma[q] = mb[q] = false;
+      if constexpr (FS) {
+        ma[q] = load_or0(mask, ia, sf, in) != 0;
+        mb[q] = load_or0(mask, ib, sf, inb) != 0;
+      } else {
+        ga[q] = load_or0(g, ia, sf, in);
+        gb[q] = load_or0(g, ib, sf, inb);
+      }
     }
+  }
+  template <int NTHR>
+  __device__ bool decide(double* red) {
+    a_dp = a_p = a_ol = 0.0;
+    double tot[2];
+    dots.template total<NTHR>(part + kPartDots, nb, red, tot);
+    tau = (it > 0 && tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
     return true;
   }
   __device__ __forceinline__ T upd(T po, T tv, T gv, bool in_set) {
@@ -187,29 +251,11 @@ struct UpdatePro {
     return pt;
   }
   template <int NTHR>
-  __device__ void load(int ya, int yb, bool hasb, int nxl, T (&va)[PER], T (&vb)[PER]) {
-    T ta[PER], tb[PER], ga[PER], gb[PER];
-    bool ma[PER], mb[PER];
+  __device__ void make(int, int, bool hasb, int nxl, T (&va)[PER], T (&vb)[PER]) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int n = threadIdx.x + q * NTHR;
-      const bool in = n < nxl, inb = in && hasb;
-      const size_t ia = (size_t)ya * nx + n, ib = (size_t)yb * nx + n;
-      va[q] = in ? p[ia] : T(0);
-      vb[q] = inb ? p[ib] : T(0);
-      ta[q] = tb[q] = ga[q] = gb[q] = T(0);
-      ma[q] = mb[q] = false;
-      if (it > 0) {
-        ta[q] = in ? t[ia] : T(0);
-        tb[q] = inb ? t[ib] : T(0);
-        if constexpr (FS) {
-          ma[q] = in && mask[ia];
-          mb[q] = inb && mask[ib];
-        } else {
-          ga[q] = in ? g[ia] : T(0);
-          gb[q] = inb ? g[ib] : T(0);
-        }
-      }
+      va[q] = pa[q];
+      vb[q] = pb[q];
     }
     if (it == 0) {
 #pragma unroll
@@ -266,15 +312,15 @@ struct GapEpi {
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       const bool in = n < nxl, inb = in && hasb;
-      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
-      ha[q] = in ? hd[a] : T(0);
-      hb[q] = inb ? hd[b] : T(0);
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
+      ha[q] = load_or0(hd, a, sf, in);
+      hb[q] = load_or0(hd, b, sf, inb);
       if constexpr (FS) {
-        ca[q] = in && mask[a];
-        cb[q] = inb && mask[b];
+        ca[q] = load_or0(mask, a, sf, in) != 0;
+        cb[q] = load_or0(mask, b, sf, inb) != 0;
       } else {
-        ca[q] = in && p[a] > T(0);
-        cb[q] = inb && p[b] > T(0);
+        ca[q] = load_or0(p, a, sf, in) > T(0);
+        cb[q] = load_or0(p, b, sf, inb) > T(0);
       }
     }
   }
@@ -324,12 +370,42 @@ struct DirPro {
   double* part;
   int nx, nb, it;
   double ratio;
+  T ga[PER], gb[PER], ta[PER], tb[PER];
+  bool ca[PER], cb[PER];
+  Partials<3> pu;
+  Partials<2> pg;
   template <int NTHR>
-  __device__ bool begin(double* red) {
+  __device__ bool issue() {
     if (sc->done) return false;
+    pu.template issue<NTHR>(part + kPartUpd, nb);
+    pg.template issue<NTHR>(part + kPartGap, nb);
+    return true;
+  }
+  template <int NTHR>
+  __device__ void fetch(int ya, int yb, bool hasb, int nxl) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const bool in = n < nxl, inb = in && hasb;
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
+      ga[q] = load_or0(g, a, sf, in);
+      gb[q] = load_or0(g, b, sf, inb);
+      ta[q] = load_or0(t, a, sf, in);
+      tb[q] = load_or0(t, b, sf, inb);
+      if constexpr (FS) {
+        ca[q] = load_or0(mask, a, sf, in) != 0;
+        cb[q] = load_or0(mask, b, sf, inb) != 0;
+      } else {
+        ca[q] = load_or0(p, a, sf, in) > T(0);
+        cb[q] = load_or0(p, b, sf, inb) > T(0);
+      }
+    }
+  }
+  template <int NTHR>
+  __device__ bool decide(double* red) {
     double up[3], gp[2];
-    read_totals<3, NTHR>(part + kPartUpd, nb, red, up);
-    read_totals<2, NTHR>(part + kPartGap, nb, red, gp);
+    pu.template total<NTHR>(part + kPartUpd, nb, red, up);
+    pg.template total<NTHR>(part + kPartGap, nb, red, gp);
     const double G = gp[0], rhs2 = gp[1];
     const double sum_dp = up[0], sum_p = up[1], n_ol = up[2];
     const double G_old = it > 0 ? sc->G_hist[(it - 1) & 1] : 1.0;
@@ -374,26 +450,7 @@ struct DirPro {
     return true;
   }
   template <int NTHR>
-  __device__ void load(int ya, int yb, bool hasb, int nxl, T (&va)[PER], T (&vb)[PER]) {
-    T ga[PER], gb[PER], ta[PER], tb[PER];
-    bool ca[PER], cb[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int n = threadIdx.x + q * NTHR;
-      const bool in = n < nxl, inb = in && hasb;
-      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
-      ga[q] = in ? g[a] : T(0);
-      gb[q] = inb ? g[b] : T(0);
-      ta[q] = in ? t[a] : T(0);
-      tb[q] = inb ? t[b] : T(0);
-      if constexpr (FS) {
-        ca[q] = in && mask[a];
-        cb[q] = inb && mask[b];
-      } else {
-        ca[q] = in && p[a] > T(0);
-        cb[q] = inb && p[b] > T(0);
-      }
-    }
+  __device__ void make(int, int, bool, int, T (&va)[PER], T (&vb)[PER]) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       va[q] = ca[q] ? (T)((double)ga[q] + ratio * (double)ta[q]) : T(0);
@@ -434,11 +491,11 @@ struct DotsEpi {
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       const bool in = n < nxl, inb = in && hasb;
-      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n;
-      ga_[q] = in ? g[a] : T(0);
-      ta_[q] = in ? t[a] : T(0);
-      gb_[q] = inb ? g[b] : T(0);
-      tb_[q] = inb ? t[b] : T(0);
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
+      ga_[q] = load_or0(g, a, sf, in);
+      ta_[q] = load_or0(t, a, sf, in);
+      gb_[q] = load_or0(g, b, sf, inb);
+      tb_[q] = load_or0(t, b, sf, inb);
     }
   }
   template <int NTHR>

@@ -30,6 +30,16 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
 
 // LDS index padding: one spare slot every 32 elements breaks the power-of-two
 // strides of the Stockham write pattern across the LDS banks.
+// Guarded load without control flow: reads a[ok ? i : safe] (safe must be a
+// valid index) and returns zero where !ok.  A load under an `if` becomes a
+// branch whose value the compiler waits for inside it, which serialises the
+// loads of a thread; this form keeps them all in flight.
+template <typename T>
+__device__ __forceinline__ T load_or0(const T* __restrict__ a, size_t i, size_t safe, bool ok) {
+  const T v = a[ok ? i : safe];
+  return ok ? v : T(0);
+}
+
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
 __host__ __device__ constexpr int lds_len(int n) { return n + (n >> 5) + 1; }
 

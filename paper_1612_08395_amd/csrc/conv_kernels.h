@@ -38,9 +38,15 @@ namespace bem {
 
 // Functor interface of the row sweeps.  Each thread handles the elements
 // n = threadIdx.x + q NTHR (q < PER) of the workgroup's two rows ya, yb.
-//  prologue (R2C): begin<NTHR>(red) -> false: the whole workgroup returns;
-//    load<NTHR>(ya, yb, hasb, nx, va, vb): all reads, values to transform
-//    (zero for n >= nx); commit<NTHR>(...): writes back updated state;
+//  prologue (R2C), called in this order so that the field loads are in
+//    flight while scalars are reduced:
+//    issue<NTHR>() -> false: the whole workgroup returns; else issues the
+//      loads of any partial sums the prologue needs;
+//    fetch<NTHR>(ya, yb, hasb, nx): issues the field loads;
+//    decide<NTHR>(red) -> false: the whole workgroup returns (reduces the
+//      partial sums; every workgroup reaches the same decision);
+//    make<NTHR>(ya, yb, hasb, nx, va, vb): values to transform (zero for
+//      n >= nx); commit<NTHR>(...): writes back updated state;
 //    finish<NTHR>(red): per-workgroup partial sums.
 //  epilogue (C2R): begin, prefetch<NTHR>(ya, yb, hasb, nx) (issued before
 //    the transform so the loads overlap it), consume<NTHR>(..., va, vb)
@@ -49,15 +55,27 @@ template <typename T, int PER>
 struct PlainLoad {
   const T* in;
   int nx;
+  T fa[PER], fb[PER];
   template <int NTHR>
-  __device__ bool begin(double*) { return true; }
+  __device__ bool issue() { return true; }
   template <int NTHR>
-  __device__ void load(int ya, int yb, bool hasb, int nx_, T (&va)[PER], T (&vb)[PER]) {
+  __device__ void fetch(int ya, int yb, bool hasb, int nx_) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
-      va[q] = n < nx_ ? in[(size_t)ya * nx + n] : T(0);
-      vb[q] = (n < nx_ && hasb) ? in[(size_t)yb * nx + n] : T(0);
+      const size_t safe = (size_t)ya * nx;
+      fa[q] = load_or0(in, (size_t)ya * nx + n, safe, n < nx_);
+      fb[q] = load_or0(in, (size_t)yb * nx + n, safe, n < nx_ && hasb);
+    }
+  }
+  template <int NTHR>
+  __device__ bool decide(double*) { return true; }
+  template <int NTHR>
+  __device__ void make(int, int, bool, int, T (&va)[PER], T (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      va[q] = fa[q];
+      vb[q] = fb[q];
     }
   }
   template <int NTHR>
@@ -101,11 +119,13 @@ __global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restri
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
   Pro pro = pro_arg;
-  if (!pro.template begin<NTHR>(red)) return;
+  if (!pro.template issue<NTHR>()) return;
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
+  pro.template fetch<NTHR>(ya, yb, hasb, nx);
+  if (!pro.template decide<NTHR>(red)) return;
   T va[PER], vb[PER];
-  pro.template load<NTHR>(ya, yb, hasb, nx, va, vb);
+  pro.template make<NTHR>(ya, yb, hasb, nx, va, vb);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int n = threadIdx.x + q * NTHR;
@@ -240,12 +260,30 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
   if (!epi.template begin<NTHR>(red)) return;
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
-  epi.template prefetch<NTHR>(ya, yb, hasb, nx);
   const cplx<T>* Sa = S + (size_t)ya * L;
   const cplx<T>* Sb = S + (size_t)yb * L;
-  for (int k = threadIdx.x; k < L; k += NTHR) {
-    const cplx<T> A = Sa[k];
-    const cplx<T> B = hasb ? Sb[k] : cplx<T>{T(0), T(0)};
+  const cplx<T>* Sbs = hasb ? Sb : Sa;   // a valid row to read when yb is absent
+  // all loads first (no control flow between them), then the LDS scatter
+  constexpr int KPER = (L + NTHR - 1) / NTHR;
+  cplx<T> Av[KPER], Bv[KPER];
+#pragma unroll
+  for (int j = 0; j < KPER; ++j) {
+    const int k = threadIdx.x + j * NTHR;
+    const int ks = k < L ? k : 0;
+    Av[j] = Sa[ks];
+    Bv[j] = Sbs[ks];
+  }
+  // the epilogue's own loads, issued after the spectrum (in-order completion)
+  // so that they stay in flight during the transform
+  epi.template prefetch<NTHR>(ya, yb, hasb, nx);
+#pragma unroll
+  for (int j = 0; j < KPER; ++j) {
+    const int k = threadIdx.x + j * NTHR;
+    if (KPER * NTHR != L && k >= L) break;
+    const cplx<T> A = Av[j];
+    // zero row b without a branch (a select here becomes one, with a wait
+    // for every load in flight); Bv is finite data of a valid row
+    const cplx<T> B = cscale(Bv[j], hasb ? T(1) : T(0));
     if (k == 0) {
       lds[lds_pad(0)] = {A.x, B.x};        // Z[0]  = A[0]  + i B[0]
       lds[lds_pad(L / 2)] = {A.y, B.y};    // Z[Lx] = A[Lx] + i B[Lx]

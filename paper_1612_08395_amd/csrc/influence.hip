@@ -151,16 +151,28 @@ template <int PER>
 struct QLoad {
   const double* Kq;
   int nx;
+  double fa[PER], fb[PER];
   template <int NTHR>
-  __device__ bool begin(double*) { return true; }
+  __device__ bool issue() { return true; }
   template <int NTHR>
-  __device__ void load(int ya, int yb, bool hasb, int nxl, double (&va)[PER], double (&vb)[PER]) {
+  __device__ void fetch(int ya, int yb, bool hasb, int nxl) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       const double cx = n == 0 ? 0.5 : 1.0;
-      va[q] = n < nxl ? Kq[(size_t)ya * nx + n] * cx * (ya == 0 ? 0.5 : 1.0) : 0.0;
-      vb[q] = (n < nxl && hasb) ? Kq[(size_t)yb * nx + n] * cx : 0.0;
+      const size_t safe = (size_t)ya * nx;
+      fa[q] = load_or0(Kq, (size_t)ya * nx + n, safe, n < nxl) * cx * (ya == 0 ? 0.5 : 1.0);
+      fb[q] = load_or0(Kq, (size_t)yb * nx + n, safe, n < nxl && hasb) * cx;
+    }
+  }
+  template <int NTHR>
+  __device__ bool decide(double*) { return true; }
+  template <int NTHR>
+  __device__ void make(int, int, bool, int, double (&va)[PER], double (&vb)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      va[q] = fa[q];
+      vb[q] = fb[q];
     }
   }
   template <int NTHR>

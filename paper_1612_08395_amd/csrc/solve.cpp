@@ -430,8 +430,12 @@ int bem_state_create(bem_influence_t K, bem_state_t* out) {
     bem_state_free(st);
     return hip_fail(e, "pinned scalars");
   }
+  // hipMemset runs on the null stream and may return before it lands; the
+  // state is then used on the caller's stream, possibly a non-blocking one
+  // that does not order after the null stream, so wait for it here
   e = hipMemset(st->sc, 0, sizeof(CgScal));
   if (e == hipSuccess) e = hipMemset(st->mask, 0, st->n);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     bem_state_free(st);
     return hip_fail(e, "state init");
@@ -470,6 +474,9 @@ int bem_state_set(bem_state_t st, const double* p, const unsigned char* contact)
     if (!is_finite(p[i])) return set_error(BEM_EINVAL, "bem_state_set: non-finite pressure");
   hipError_t e = hipMemcpy(st->out64, p, st->n * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess && contact) e = hipMemcpy(st->mask, contact, st->n, hipMemcpyHostToDevice);
+  // a copy from pageable memory may return before the device write lands
+  // (null stream; see bem_state_create)
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return hip_fail(e, "bem_state_set");
   st->pending_import = true;
   st->import_mask = contact != nullptr;
