@@ -173,7 +173,81 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
                        f"{cores} workers) at 2048^2, depth d10, {t:.1f} s; scaled by the GPU "
                        f"FP64 mean of {iters_per_solve:.1f} iterations/solve; influence "
                        f"setup {t_setup:.1f} s not counted"),
-            "s_per_iter": round(per_iter, 4)}
+            "s_per_iter": round(per_iter, 4), "units": oracle_units(cores, Kq)}
+
+
+def big_grid(bem, torch, depths_n=5):
+    """4096^2 (8192^2 padded) rough surface, k = -0.3, nu = 0.25, seed 8395,
+    same H / q0 / q1 as the 2048^2 workload: mixed-precision indentation
+    sweep to the 10 % height quantile.  Its ~0.75 GB working set exceeds the
+    256 MB last-level cache, so this is the HBM-resident figure."""
+    from paper_1612_08395_amd import inputs
+    n = 4096
+    two_pi = 2.0 * math.pi / L
+    h = inputs.fractal_gap(n, L, H_EXP, Q0 * two_pi, Q1 * two_pi, RMS * L, 8395)
+    dq = float(np.quantile(h, 0.10))
+    h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
+    K = bem.bem_influence(n, n, L / n, -0.3, 0.25)
+    depths = [dq * s / depths_n for s in range(1, depths_n + 1)]
+
+    def sweep():
+        st = bem.bem_state_create(K)
+        res = []
+        for d in depths:
+            _, r = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=d, precision=bem.BEM_MIXED),
+                                     state=st)
+            res.append(r.as_dict())
+        st.free()
+        return res
+
+    sweep()
+    torch.cuda.synchronize()
+    bem.bem_clock_start()
+    t0 = time.perf_counter()
+    res = sweep()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    clk = bem.bem_clock_stop()
+    K.free()
+    iters = sum(r["iters"] for r in res)
+    n_col = clk.launches[1] + clk.launches[4]
+    col_ms = (clk.ms[1] + clk.ms[4]) / n_col
+    col_bytes = 2 * n * n * 8 + (n + 1) * (n + 1) * 4
+    return {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395,
+            "depths": depths_n, "d_max": dq, "solves_per_s": round(depths_n / t, 3),
+            "iters_per_solve": round(iters / depths_n, 2),
+            "loop_us_per_iteration": round(sum(clk.ms) / clk.iterations * 1e3, 2),
+            "loop_GBps_algorithmic": round(124.0 * n * n * iters / t / 1e9, 1),
+            "column_us_per_launch": round(col_ms * 1e3, 2),
+            "column_GBps_algorithmic": round(col_bytes / (col_ms * 1e-3) / 1e9, 1),
+            "contact_area_final": res[-1]["n_contact"] / float(n * n)}
+
+
+def oracle_units(cores, Kq):
+    """Further oracle timings (FP64 numpy / scipy.fft): one 2048^2
+    convolution on `cores` workers and on one, and the 128^2 Hertz-type
+    solve (k = 0.5, nu = 0.3, R = 1, side 2, d = 0.01, tol 1e-12)."""
+    from oracle import influence as inf
+    from oracle import material as m
+    from oracle import solver as so
+    from oracle.convolution import FFTConvolver
+    from paper_1612_08395_amd import inputs
+    out = {}
+    p = inputs.random_pressure(N, N, 3)
+    for w, key in ((cores, "convolution_2048_s"), (1, "convolution_2048_1thread_s")):
+        conv = FFTConvolver(Kq, m.compliance(K_EXP, NU), workers=w)
+        conv(p)
+        t0 = time.perf_counter()
+        conv(p)
+        out[key] = round(time.perf_counter() - t0, 4)
+    n1, L1 = 128, 2.0
+    dx = L1 / n1
+    Kq1 = inf.influence_quarter(n1, n1, dx, dx, 0.5)
+    h1 = inputs.parabolic(n1, L1, 1.0)
+    t0 = time.perf_counter()
+    so.solve_nonadhesive(Kq1, m.compliance(0.5, 0.3), h1, 0.01, tol=1e-12)
+    out["solve_128_hertz_s"] = round(time.perf_counter() - t0, 4)
+    return out
 
 
 def serving(count, slots, bem):
@@ -237,6 +311,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests per serving run (0: skip the serving measurement)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--no-big-grid", action="store_true",
+                    help="skip the 4096^2 (HBM-resident) mixed sweep")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
                          "and a 1 GiB device copy, for hardware-counter runs")
@@ -313,6 +389,14 @@ def main():
                           "status_mixed": sorted({x["status"] for x in res32[-1]})},
         "contact_area_final": res32[-1][-1]["n_contact"] / float(N * N),
     }
+    # compulsory traffic: each convolution reads its input and the kernel
+    # spectrum quarter and writes its output (12 B per element in FP32)
+    comp = 24.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
+    out["compulsory_GBps"] = round(comp, 1)
+    out["compulsory_frac"] = round(comp / HBM_PEAK_GBS, 4)
+    if not args.no_big_grid:
+        log("[bench] 4096^2 sweep")
+        out["hbm_resident_4096"] = big_grid(bem, torch)
     if args.serving_requests > 0:
         log("[bench] serving")
         out["serving"] = serving(args.serving_requests, args.serving_slots, bem)

@@ -37,6 +37,24 @@ stress exceeds p_crit (-p > p_crit, strict) leaves A, all at once; the
 solve is repeated on the reduced set until no element violates the
 criterion.  Force F = Dx Dy sum p.
 
+Load-controlled non-adhesive contact (the form of the cited method in
+which the total force W is prescribed and the indentation is an unknown).
+With gh = u + h (the gap up to the unknown rigid approach):
+
+  repeat
+    u = C K * p ;  Ic = {p > 0} ;  gbar = mean_Ic gh ;  g = gh - gbar
+    G = sum_Ic g^2
+    t = g + delta (G / G_old) t on Ic, 0 elsewhere ;  G_old = G
+    r = C K * t ;  r <- r - mean_Ic r ;  tau = sum_Ic g t / sum_Ic r t
+    p <- p - tau t on Ic ;  p <- max(p, 0) ;  overlap step as above
+    p <- p W / (Dx Dy sum p)
+  until sqrt(G) <= tol ||u_Ic||, Iol is empty and
+        sum |p_new - p_old| <= tol sum |p_new|
+
+The indentation is d = gbar: on Ic the gap u + h - d vanishes.  The cold
+start is a uniform pressure carrying W.  (Reading: the stopping test is the
+displacement-controlled one, with the contact displacement as its scale.)
+
 Pins (tests/test_oracle_solver.py): KKT conditions with a direct-sum
 residual; cold and warm starts agree; four-fold symmetry of a centred
 indenter; Hertz (k = 0) force and radius; power-law Hertz-type radius
@@ -158,6 +176,67 @@ def adhesive_step(Kq, C, h, d, A, p_init, pcrit, tol=1e-12, max_iter=20000, conv
         A = A & ~V
         p = np.where(A, res.p, 0.0)
         rounds += 1
+
+
+def solve_force(Kq, C, h, W, dx, dy, tol=1e-12, max_iter=20000, p_init=None, conv=None):
+    """Load-controlled non-adhesive solve (see module docstring).  Returns a
+    SolveResult with the indentation in .d."""
+    h = np.asarray(h, dtype=np.float64)
+    conv = conv or FFTConvolver(Kq, C)
+    if W <= 0.0:
+        z = np.zeros_like(h)
+        res = SolveResult(z, h - h.min(), z.copy(), 0, True, z > 0)
+        res.d = float(h.min())
+        return res
+    P_target = W / (dx * dy)
+    if p_init is None or not np.any(np.asarray(p_init) > 0):
+        p = np.full_like(h, P_target / h.size)
+    else:
+        p = np.maximum(np.asarray(p_init, dtype=np.float64), 0.0)
+        p = p * (P_target / np.sum(p))
+    delta = 0.0
+    G_old = 1.0
+    t = np.zeros_like(p)
+    n_ol, sum_dp, sum_p = 0, np.inf, 1.0
+    it = 0
+    converged = False
+    while True:
+        u = conv(p)
+        gh = u + h
+        Ic = p > 0
+        gbar = float(np.mean(gh[Ic]))
+        g = gh - gbar
+        G = float(np.sum(g[Ic] ** 2))
+        unorm = float(np.sqrt(np.sum(u[Ic] ** 2)))
+        if it > 0 and np.sqrt(G) <= tol * unorm and n_ol == 0 and sum_dp <= tol * sum_p:
+            converged = True
+            break
+        if it >= max_iter:
+            break
+        it += 1
+        ratio = G / G_old if G_old > 0 else 0.0
+        t = np.where(Ic, g + delta * ratio * t, 0.0)
+        G_old = G
+        r = conv(t)
+        r = r - float(np.mean(r[Ic]))
+        rt = float(np.sum(r[Ic] * t[Ic]))
+        tau = float(np.sum(g[Ic] * t[Ic])) / rt if rt != 0.0 else 0.0
+        p_old = p
+        p = np.where(Ic, p - tau * t, p)
+        p = np.maximum(p, 0.0)
+        ol = (p == 0.0) & (g < 0.0)
+        n_ol = int(np.count_nonzero(ol))
+        if n_ol == 0:
+            delta = 1.0
+        else:
+            delta = 0.0
+            p = np.where(ol, p - tau * g, p)
+        p = p * (P_target / np.sum(p))
+        sum_dp = float(np.sum(np.abs(p - p_old)))
+        sum_p = float(np.sum(np.abs(p)))
+    res = SolveResult(p, g, u, it, converged, p > 0)
+    res.d = gbar
+    return res
 
 
 def force(p, dx, dy):

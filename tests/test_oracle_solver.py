@@ -170,3 +170,69 @@ def test_flat_punch_pulloff_k0_kendall():
             break
     assert not A.any()
     assert -Fmin == pytest.approx(Fc, rel=0.05)
+
+
+# ---- load control ------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [-0.4, 0.3])
+def test_force_control_kkt_with_direct_sum_residual(k):
+    n, L, R = 40, 1.0, 1.0
+    dx, Kq, C = _setup(n, L, k)
+    h = inputs.parabolic(n, L, R)
+    W = 6e-3
+    res = so.solve_force(Kq, C, h, W, dx, dx, tol=1e-13)
+    assert res.converged
+    p, d = res.p, res.d
+    assert so.force(p, dx, dx) == pytest.approx(W, rel=1e-13)   # the load constraint
+    g = conv_direct(Kq, p, C) + h - d          # independent residual, d from the solve
+    assert p.min() >= 0.0
+    assert g.min() >= -1e-10 * d
+    assert np.max(np.abs(g[p > 0])) <= 1e-10 * d
+    assert 40 < np.count_nonzero(p) < n * n / 2
+
+
+def test_force_control_hertz_k0():
+    # Classical Hertz under a given load: a = (3 F R / (4 E*))^(1/3), d = a^2 / R.
+    n, L, R, nu = 128, 2.0, 1.0, 0.3
+    dx, Kq, C = _setup(n, L, 0.0, nu)
+    Estar = 1.0 / (1 - nu * nu)
+    a = 0.1
+    W = 4 * Estar * a ** 3 / (3 * R)
+    res = so.solve_force(Kq, C, inputs.parabolic(n, L, R), W, dx, dx)
+    assert res.d == pytest.approx(a * a / R, rel=3e-3)
+    a_num = math.sqrt(res.contact.sum() * dx * dx / math.pi)
+    assert abs(a_num - a) < dx
+
+
+@pytest.mark.parametrize("k", [-0.5, 0.5])
+def test_force_control_hertz_type_power_law(k):
+    # load from the reading of Eq. 16 at radius a; indentation from Eq. 15
+    n, L, R, nu = 128, 2.0, 1.0, 0.3
+    dx, Kq, C = _setup(n, L, k, nu)
+    a = 0.1
+    W = an.hertz_force(k, nu, R, a)
+    res = so.solve_force(Kq, C, inputs.parabolic(n, L, R), W, dx, dx)
+    assert res.d == pytest.approx(a * a / ((1 + k) * R), rel=1e-2)
+    a_num = math.sqrt(res.contact.sum() * dx * dx / math.pi)
+    assert abs(a_num - a) < dx
+
+
+def test_force_and_displacement_control_agree():
+    # the solution is unique: the load of a displacement-controlled solve,
+    # prescribed, gives back its pressure and indentation
+    n, L, k = 64, 1.0, 0.2
+    dx, Kq, C = _setup(n, L, k)
+    h = inputs.fractal_gap(n, L, 0.7, 4 * 2 * math.pi, 16 * 2 * math.pi, 1e-3, 11)
+    d = float(np.quantile(h, 0.08))
+    a = so.solve_nonadhesive(Kq, C, h, d, tol=1e-13)
+    b = so.solve_force(Kq, C, h, so.force(a.p, dx, dx), dx, dx, tol=1e-13)
+    assert b.d == pytest.approx(d, rel=1e-9)
+    assert np.linalg.norm(a.p - b.p) <= 1e-8 * np.linalg.norm(a.p)
+    assert np.array_equal(a.contact, b.contact)
+
+
+def test_force_control_zero_load():
+    n, L = 16, 1.0
+    dx, Kq, C = _setup(n, L, 0.0)
+    res = so.solve_force(Kq, C, inputs.parabolic(n, L, 1.0), 0.0, dx, dx)
+    assert not res.p.any() and res.converged
