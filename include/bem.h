@@ -123,11 +123,12 @@ typedef struct bem_state_s* bem_state_t;
 enum { BEM_CTRL_INDENT = 0, BEM_CTRL_FORCE = 1 };
 
 typedef struct {
-  int control;       /* BEM_CTRL_INDENT: indentation d given (BEM_CTRL_FORCE: not
-                        implemented, returns BEM_EUNSUPPORTED) */
+  int control;       /* BEM_CTRL_INDENT: indentation d given; BEM_CTRL_FORCE:
+                        normal force F given, d found (non-adhesive only) */
   int precision;     /* BEM_FP64 or BEM_MIXED */
   double d;          /* indentation: rigid-body approach of the indenter */
-  double F;          /* target normal force (BEM_CTRL_FORCE) */
+  double F;          /* prescribed normal force dx dy sum p (BEM_CTRL_FORCE),
+                        >= 0 */
   double gamma;      /* work of adhesion gamma12 (Eq. 20); 0 = non-adhesive */
   double p_crit;     /* > 0: detachment stress used as given; <= 0: from gamma
                         by Eq. 24 with the corrected c1(k) of Table 1 */
@@ -148,8 +149,10 @@ void bem_params_init(bem_params* prm);
 typedef struct {
   double F;                  /* normal force dx dy sum p (FP64 sum) */
   double area;               /* contact area: contact elements * dx dy */
-  double d;                  /* indentation of this solve */
-  double residual;           /* final sqrt(sum_Ic g^2) / sqrt(sum_Ic (d-h)^2) */
+  double d;                  /* indentation of this solve (found, under force
+                                control: the mean of u + h over the contact) */
+  double residual;           /* final sqrt(sum_Ic g^2) / sqrt(sum_Ic (d-h)^2)
+                                (force control: / sqrt(sum_Ic u^2)) */
   double p_crit;             /* detachment stress used (adhesive), else 0 */
   long long n_contact;       /* elements in contact */
   long long n_penetrating;   /* adhesive: elements off the contact set with g < 0 */
@@ -173,14 +176,21 @@ int bem_state_get(bem_state_t st, double* p, unsigned char* contact);
 int bem_state_reset(bem_state_t st);
 
 /*
- * bem_solve -- one contact solve at indentation prm->d for the gap profile h
- * (host, ny x nx FP64, the gap between the undeformed surfaces).
+ * bem_solve -- one contact solve at indentation prm->d (or under the normal
+ * force prm->F) for the gap profile h (host, ny x nx FP64, the gap between
+ * the undeformed surfaces).
  *
  * Non-adhesive (gamma = 0 and p_crit <= 0): pressure p >= 0 with g = 0 where
  * p > 0 and g >= 0 elsewhere, by the constrained conjugate-gradient method
  * the paper uses for its inverse problem (Section 2.1), displacement
  * controlled.  The solution is unique; a warm start changes only the
  * iteration count.
+ *
+ * Force control (control = BEM_CTRL_FORCE, the problem statement of Section
+ * 2.2 with F_N given): the same method in its load-controlled form (gap
+ * shifted by its mean over the contact, pressure rescaled to carry F after
+ * each update); res->d returns the indentation found.  Cold start: uniform
+ * pressure.  F = 0: p = 0 and d = min h.  Non-adhesive only.
  *
  * Adhesive (gamma > 0 or p_crit > 0), one pull-off step of Section 3.1: with
  * the state's contact set A held fixed, u = d - h on A and p = 0 off A; then
@@ -194,7 +204,7 @@ int bem_state_reset(bem_state_t st);
  * displacement): host ny x nx arrays or NULL.  res: may be NULL.
  * Returns BEM_OK, BEM_ENOCONV / BEM_EFLOOR (warnings; outputs hold the last
  * iterate), BEM_ENUMERIC, BEM_EINVAL (non-finite h or d, bad parameters),
- * BEM_EUNSUPPORTED (force control; adhesion with dx != dy).
+ * BEM_EUNSUPPORTED (force control with adhesion; adhesion with dx != dy).
  */
 int bem_solve(bem_influence_t K, const double* h, const bem_params* prm, bem_state_t state,
               double* p_out, unsigned char* contact_out, double* u_out, bem_result* res,
@@ -208,7 +218,8 @@ int bem_solve_dev(bem_influence_t K, const double* h, const bem_params* prm, bem
                   void* stream);
 
 /*
- * bem_sweep -- a sequence of solves at the indentations d_list[0..n_steps),
+ * bem_sweep -- a sequence of solves at the indentations d_list[0..n_steps)
+ * (under force control: at the normal forces d_list[0..n_steps)),
  * warm-started from step to step on the device (Section 3.1).  With
  * adhesion, a step whose d is below the previous step's is a pull-off step
  * (adhesive solve); every other step is a non-adhesive (loading) solve.

@@ -14,6 +14,13 @@
 // Non-adhesive mode: Ic = {p > 0}, projection and overlap step as above.
 // Fixed-set mode (adhesive contact, Section 3.1): Ic = the contact set A,
 // no projection, no overlap step, delta = 1 after the first iteration.
+// Load-control mode (non-adhesive, total force W prescribed, d unknown):
+// g is shifted by its mean over Ic (gbar, which becomes the indentation),
+// r by its mean over Ic, and p is rescaled to carry W after each update.
+// The rescaling is deferred: K1 stores the unscaled update p' and its sum;
+// K3 scales u by s = W / sum p' (linearity) and the next K1 scales p' by the
+// same s on reading.  G = sum_Ic (g - gbar)^2 is formed from sums shifted by
+// the previous gbar, which keeps the subtraction benign near convergence.
 //
 // One iteration is six kernel launches; the vector work is fused into the
 // row sweeps of the two convolutions:
@@ -53,7 +60,15 @@ struct CgScal {
   // final sums of the elementwise kernels
   double fin_sum_p, fin_contact, fin_pen, fin_detach;
   unsigned int ticket[8];
+  // load control: prescribed sum of p (F / (dx dy)); K4 history (slot
+  // it & 1) of the mean gap over Ic, the load scale and |Ic|; values at the
+  // stopping iteration
+  double W;
+  double gbar_hist[2], scale_hist[2], nc_hist[2];
+  double gbar, scale;
 };
+
+enum { CG_DISP = 0, CG_FIXED = 1, CG_FORCE = 2 };
 
 enum { CG_ST_OK = 0, CG_ST_NOCONV = 1, CG_ST_FLOOR = 2, CG_ST_NUMERIC = -5 };
 
@@ -61,8 +76,11 @@ enum { CG_ST_OK = 0, CG_ST_NOCONV = 1, CG_ST_FLOOR = 2, CG_ST_NUMERIC = -5 };
 constexpr int kMaxRowBlocks = 2048;
 constexpr int kPartUpd = 0;                      // 3 values: sum|dp|, sum|p|, n_ol
 constexpr int kPartGap = 3 * kMaxRowBlocks;      // 2 values: sum_Ic g^2, sum_Ic (h-d)^2
-constexpr int kPartDots = 5 * kMaxRowBlocks;     // 2 values: sum g t, sum r t
-constexpr int kPartElem = 7 * kMaxRowBlocks;     // elementwise kernels (3 values x 1024)
+                                                 // load control, 4: sum_Ic e, sum_Ic e^2,
+                                                 // |Ic|, sum_Ic u^2 (e = g - previous gbar)
+constexpr int kPartDots = 7 * kMaxRowBlocks;     // 2 values: sum g t, sum r t; load
+                                                 // control, 4: + sum t, sum_Ic r
+constexpr int kPartElem = 11 * kMaxRowBlocks;    // elementwise kernels (3 values x 1024)
 constexpr int kPartTotal = kPartElem + 3 * 1024;
 
 // Block sums of NV values (result in every thread), one barrier pair.
@@ -180,8 +198,10 @@ __device__ __forceinline__ bool grid_reduce_last(const double (&acc)[NV], double
 }
 
 // K1 prologue: p update with the previous iteration's tau, t and g.
-template <typename T, bool FS, int PER>
+template <typename T, int MODE, int PER>
 struct UpdatePro {
+  static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
+  static constexpr int NVD = FC ? 4 : 2;
   T* p;
   const T* t;
   const T* g;
@@ -190,9 +210,10 @@ struct UpdatePro {
   double* part;
   int nx, nb, it;
   double tau, a_dp, a_p, a_ol;
+  double sprev, gshift;  // load control: scale of the stored p, mean gap
   T pa[PER], pb[PER], ta[PER], tb[PER], ga[PER], gb[PER];
   bool ma[PER], mb[PER];
-  Partials<2> dots;
+  Partials<NVD> dots;
   template <int NTHR>
   __device__ bool issue() {
     if (sc->done) return false;
@@ -228,25 +249,38 @@ struct UpdatePro {
   template <int NTHR>
   __device__ bool decide(double* red) {
     a_dp = a_p = a_ol = 0.0;
-    double tot[2];
+    double tot[NVD];
     dots.template total<NTHR>(part + kPartDots, nb, red, tot);
-    tau = (it > 0 && tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
+    if constexpr (FC) {
+      const int j = (it - 1) & 1;
+      sprev = it > 0 ? sc->scale_hist[j] : 1.0;
+      gshift = it > 0 ? sc->gbar_hist[j] : 0.0;
+      const double nc = it > 0 ? sc->nc_hist[j] : 0.0;
+      // sum_Ic (r - rbar) t = sum r t - rbar sum t   (t = 0 off Ic)
+      const double den = tot[1] - (nc > 0.0 ? tot[3] / nc : 0.0) * tot[2];
+      tau = (it > 0 && den != 0.0) ? tot[0] / den : 0.0;
+    } else {
+      sprev = 1.0;
+      gshift = 0.0;
+      tau = (it > 0 && tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
+    }
     return true;
   }
-  __device__ __forceinline__ T upd(T po, T tv, T gv, bool in_set) {
-    double pn = (double)po;
+  __device__ __forceinline__ T upd(double po, T tv, T gv, bool in_set) {
+    double pn = po;
     if constexpr (FS) {
-      if (in_set) pn = (double)po - tau * (double)tv;
+      if (in_set) pn = po - tau * (double)tv;
     } else {
-      if (po > T(0)) pn = (double)po - tau * (double)tv;
+      const double gs = (double)gv - gshift;
+      if (po > 0.0) pn = po - tau * (double)tv;
       if (pn < 0.0) pn = 0.0;
-      if (pn == 0.0 && gv < T(0)) {
-        pn = -tau * (double)gv;
+      if (pn == 0.0 && gs < 0.0) {
+        pn = -tau * gs;
         a_ol += 1.0;
       }
     }
     const T pt = (T)pn;
-    a_dp += fabs((double)pt - (double)po);
+    a_dp += fabs((double)pt - po);
     a_p += fabs((double)pt);
     return pt;
   }
@@ -266,8 +300,8 @@ struct UpdatePro {
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       if (n < nxl) {
-        va[q] = upd(va[q], ta[q], ga[q], ma[q]);
-        if (hasb) vb[q] = upd(vb[q], tb[q], gb[q], mb[q]);
+        va[q] = upd(sprev * (double)va[q], ta[q], ga[q], ma[q]);
+        if (hasb) vb[q] = upd(sprev * (double)vb[q], tb[q], gb[q], mb[q]);
       }
     }
   }
@@ -291,21 +325,31 @@ struct UpdatePro {
   }
 };
 
-// K3 epilogue: g = u + (h - d) and the partial sums of g^2, (h - d)^2 on Ic.
-template <typename T, bool FS, int PER>
+// K3 epilogue: g = u + (h - d) and the partial sums for G and its scale on
+// Ic.  Load control: u is first scaled by s = W / sum p (K1's partials) and
+// the sums are of e = g - (previous gbar), with |Ic| and sum_Ic u^2.
+template <typename T, int MODE, int PER>
 struct GapEpi {
+  static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
+  static constexpr int NV = FC ? 4 : 2;
   T* g;
   const T* hd;
   const T* p;
   const uint8_t* mask;
   const CgScal* sc;
   double* part;
-  int nx;
+  int nx, nb, it;
   T ha[PER], hb[PER];
   bool ca[PER], cb[PER];
-  double a_G, a_r;
+  double acc[NV];
+  double s, gref;
+  Partials<3> pu;
   template <int NTHR>
-  __device__ bool begin(double*) { return sc->done == 0; }
+  __device__ bool begin(double*) {
+    if (sc->done) return false;
+    if constexpr (FC) pu.template issue<NTHR>(part + kPartUpd, nb);
+    return true;
+  }
   template <int NTHR>
   __device__ void prefetch(int ya, int yb, bool hasb, int nxl) {
 #pragma unroll
@@ -324,44 +368,63 @@ struct GapEpi {
       }
     }
   }
+  // after the loads are issued: the reductions the epilogue needs
+  template <int NTHR>
+  __device__ void ready(double* red) {
+    if constexpr (FC) {
+      double up[3];
+      pu.template total<NTHR>(part + kPartUpd, nb, red, up);
+      s = sc->W / up[1];
+      gref = it > 0 ? sc->gbar_hist[(it - 1) & 1] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void one(size_t i, T u, T h, bool c) {
+    if constexpr (FC) {
+      const double us = s * (double)u;
+      const T gv = (T)(us + (double)h);
+      g[i] = gv;
+      if (c) {
+        const double e = (double)gv - gref;
+        acc[0] += e;
+        acc[1] += e * e;
+        acc[2] += 1.0;
+        acc[3] += us * us;
+      }
+    } else {
+      const T gv = (T)((double)u + (double)h);
+      g[i] = gv;
+      if (c) {
+        acc[0] += (double)gv * (double)gv;
+        acc[1] += (double)h * (double)h;
+      }
+    }
+  }
   template <int NTHR>
   __device__ void consume(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
                           const T (&vb)[PER]) {
-    double aG = 0.0, ar = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       if (n < nxl) {
-        const T ga = (T)((double)va[q] + (double)ha[q]);
-        g[(size_t)ya * nx + n] = ga;
-        if (ca[q]) {
-          aG += (double)ga * (double)ga;
-          ar += (double)ha[q] * (double)ha[q];
-        }
-        if (hasb) {
-          const T gb = (T)((double)vb[q] + (double)hb[q]);
-          g[(size_t)yb * nx + n] = gb;
-          if (cb[q]) {
-            aG += (double)gb * (double)gb;
-            ar += (double)hb[q] * (double)hb[q];
-          }
-        }
+        one((size_t)ya * nx + n, va[q], ha[q], ca[q]);
+        if (hasb) one((size_t)yb * nx + n, vb[q], hb[q], cb[q]);
       }
     }
-    a_G = aG;
-    a_r = ar;
   }
   template <int NTHR>
   __device__ void finish(double* red) {
-    double acc[2] = {a_G, a_r};
-    write_partials<2, NTHR>(acc, red, part + kPartGap);
+    write_partials<NV, NTHR>(acc, red, part + kPartGap);
   }
 };
 
 // K4 prologue: convergence decision (stopping test at the current iterate,
 // iteration limit, non-finite values, MIXED stagnation), then t.
-template <typename T, bool FS, int PER>
+template <typename T, int MODE, int PER>
 struct DirPro {
+  static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
+  static constexpr int NVG = FC ? 4 : 2;
   T* t;
   const T* g;
   const T* p;
@@ -369,11 +432,11 @@ struct DirPro {
   CgScal* sc;
   double* part;
   int nx, nb, it;
-  double ratio;
+  double ratio, gbar;
   T ga[PER], gb[PER], ta[PER], tb[PER];
   bool ca[PER], cb[PER];
   Partials<3> pu;
-  Partials<2> pg;
+  Partials<NVG> pg;
   template <int NTHR>
   __device__ bool issue() {
     if (sc->done) return false;
@@ -403,16 +466,28 @@ struct DirPro {
   }
   template <int NTHR>
   __device__ bool decide(double* red) {
-    double up[3], gp[2];
+    double up[3], gp[NVG];
     pu.template total<NTHR>(part + kPartUpd, nb, red, up);
     pg.template total<NTHR>(part + kPartGap, nb, red, gp);
-    const double G = gp[0], rhs2 = gp[1];
     const double sum_dp = up[0], sum_p = up[1], n_ol = up[2];
+    double G, rhs2, scale = 1.0, nc = 0.0;
+    gbar = 0.0;
+    if constexpr (FC) {
+      const double gref = it > 0 ? sc->gbar_hist[(it - 1) & 1] : 0.0;
+      nc = gp[2];
+      gbar = nc > 0.0 ? gref + gp[0] / nc : gref;
+      G = nc > 0.0 ? fmax(gp[1] - gp[0] * gp[0] / nc, 0.0) : 0.0;
+      rhs2 = gp[3];
+      scale = sc->W / sum_p;
+    } else {
+      G = gp[0];
+      rhs2 = gp[1];
+    }
     const double G_old = it > 0 ? sc->G_hist[(it - 1) & 1] : 1.0;
     double best = it > 0 ? sc->best_hist[(it - 1) & 1] : 1e300;
     int stall = it > 0 ? sc->stall_hist[(it - 1) & 1] : 0;
     int done = 0, status = CG_ST_OK;
-    if (!isfinite(G) || !isfinite(sum_p)) {
+    if (!isfinite(G) || !isfinite(sum_p) || !isfinite(scale)) {
       done = 1;
       status = CG_ST_NUMERIC;
     } else if (it > 0 && sqrt(G) <= sc->tol * sqrt(rhs2) && n_ol == 0.0 &&
@@ -431,12 +506,19 @@ struct DirPro {
       }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if constexpr (FC) {
+        sc->gbar_hist[it & 1] = gbar;
+        sc->scale_hist[it & 1] = scale;
+        sc->nc_hist[it & 1] = nc;
+      }
       if (done) {
         sc->status = status;
         sc->iter = it;
         sc->G = G;
         sc->rhs2 = rhs2;
         sc->sum_p = sum_p;
+        sc->gbar = gbar;
+        sc->scale = scale;
         sc->done = 1;
       } else {
         sc->G_hist[it & 1] = G;
@@ -453,8 +535,8 @@ struct DirPro {
   __device__ void make(int, int, bool, int, T (&va)[PER], T (&vb)[PER]) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      va[q] = ca[q] ? (T)((double)ga[q] + ratio * (double)ta[q]) : T(0);
-      vb[q] = cb[q] ? (T)((double)gb[q] + ratio * (double)tb[q]) : T(0);
+      va[q] = ca[q] ? (T)((double)ga[q] - gbar + ratio * (double)ta[q]) : T(0);
+      vb[q] = cb[q] ? (T)((double)gb[q] - gbar + ratio * (double)tb[q]) : T(0);
     }
   }
   template <int NTHR>
@@ -474,17 +556,28 @@ struct DirPro {
 };
 
 // K6 epilogue: sum g t and sum r t (t = 0 off Ic, so no mask is needed).
-template <typename T, int PER>
+// Load control: g is shifted by gbar, and sum t, sum_Ic r (Ic = {p > 0})
+// give the shift of r by its mean over Ic.
+template <typename T, int MODE, int PER>
 struct DotsEpi {
+  static constexpr bool FC = MODE == CG_FORCE;
+  static constexpr int NV = FC ? 4 : 2;
   const T* g;
   const T* t;
+  const T* p;
   const CgScal* sc;
   double* part;
-  int nx;
+  int nx, it;
   T ga_[PER], gb_[PER], ta_[PER], tb_[PER];
-  double a_gt, a_rt;
+  bool ca[PER], cb[PER];
+  double acc[NV];
+  double gbar;
   template <int NTHR>
-  __device__ bool begin(double*) { return sc->done == 0; }
+  __device__ bool begin(double*) {
+    if (sc->done) return false;
+    gbar = FC ? sc->gbar_hist[it & 1] : 0.0;
+    return true;
+  }
   template <int NTHR>
   __device__ void prefetch(int ya, int yb, bool hasb, int nxl) {
 #pragma unroll
@@ -496,23 +589,32 @@ struct DotsEpi {
       ta_[q] = load_or0(t, a, sf, in);
       gb_[q] = load_or0(g, b, sf, inb);
       tb_[q] = load_or0(t, b, sf, inb);
+      ca[q] = cb[q] = false;
+      if constexpr (FC) {
+        ca[q] = load_or0(p, a, sf, in) > T(0);
+        cb[q] = load_or0(p, b, sf, inb) > T(0);
+      }
     }
   }
   template <int NTHR>
+  __device__ void ready(double*) {}
+  template <int NTHR>
   __device__ void consume(int, int, bool, int, const T (&va)[PER], const T (&vb)[PER]) {
-    double gt = 0.0, rt = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      gt += (double)ga_[q] * (double)ta_[q] + (double)gb_[q] * (double)tb_[q];
-      rt += (double)va[q] * (double)ta_[q] + (double)vb[q] * (double)tb_[q];
+      acc[0] += ((double)ga_[q] - gbar) * (double)ta_[q] + ((double)gb_[q] - gbar) * (double)tb_[q];
+      acc[1] += (double)va[q] * (double)ta_[q] + (double)vb[q] * (double)tb_[q];
+      if constexpr (FC) {
+        acc[2] += (double)ta_[q] + (double)tb_[q];
+        acc[3] += (ca[q] ? (double)va[q] : 0.0) + (cb[q] ? (double)vb[q] : 0.0);
+      }
     }
-    a_gt = gt;
-    a_rt = rt;
   }
   template <int NTHR>
   __device__ void finish(double* red) {
-    double acc[2] = {a_gt, a_rt};
-    write_partials<2, NTHR>(acc, red, part + kPartDots);
+    write_partials<NV, NTHR>(acc, red, part + kPartDots);
   }
 };
 
@@ -556,16 +658,23 @@ __global__ __launch_bounds__(EW_THREADS) void k_prepare(T* __restrict__ t, T* __
 
 // Final sums: sum p (force / (dx dy)), contact count, penetrations off A
 // (fixed-set mode) and the contact mask (non-adhesive mode: p > 0).
-template <typename T, bool FS>
-__global__ __launch_bounds__(EW_THREADS) void k_finalize(const T* __restrict__ p,
+template <typename T, int MODE>
+__global__ __launch_bounds__(EW_THREADS) void k_finalize(T* __restrict__ p,
                                                          const T* __restrict__ g,
                                                          uint8_t* __restrict__ mask, CgScal* sc,
                                                          double* part, size_t n) {
+  constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
   __shared__ double red[64];
   double sp = 0.0, nc = 0.0, npen = 0.0;
+  const double scale = FC ? sc->scale : 1.0;
   for (size_t i = blockIdx.x * (size_t)EW_THREADS + threadIdx.x; i < n;
        i += (size_t)gridDim.x * EW_THREADS) {
-    const T pv = p[i];
+    T pv = p[i];
+    if constexpr (FC) {
+      // load control: apply the scale of the stopping iteration
+      pv = (T)(scale * (double)pv);
+      p[i] = pv;
+    }
     sp += (double)pv;
     bool in;
     if constexpr (FS) {
@@ -584,6 +693,15 @@ __global__ __launch_bounds__(EW_THREADS) void k_finalize(const T* __restrict__ p
     sc->fin_contact = tot[1];
     sc->fin_pen = tot[2];
   }
+}
+
+// p = v everywhere (load control: cold start carrying any load; the first
+// iteration rescales it)
+template <typename T>
+__global__ __launch_bounds__(EW_THREADS) void k_fill(T* __restrict__ p, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)EW_THREADS + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * EW_THREADS)
+    p[i] = v;
 }
 
 // Detachment (Section 3.1, Eq. 24): every element of A whose tensile stress
@@ -625,6 +743,24 @@ __global__ __launch_bounds__(EW_THREADS) void k_from_f64(const double* __restric
 }
 
 // u = g - (h - d): displacement output from the last gap evaluation
+// sc->gbar = min h (load control at zero load: the surfaces just touch).
+// One workgroup of EW_THREADS.
+template <typename T>
+__global__ __launch_bounds__(EW_THREADS) void k_min_h(const double* __restrict__ h, size_t n,
+                                                      CgScal* sc) {
+  __shared__ double red[EW_THREADS / 64];
+  double m = INFINITY;
+  for (size_t i = threadIdx.x; i < n; i += EW_THREADS) m = fmin(m, h[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < EW_THREADS / 64; ++w) m = fmin(m, red[w]);
+    sc->gbar = m;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(EW_THREADS) void k_u_from_gap(const T* __restrict__ g,
                                                            const double* __restrict__ h, double d,

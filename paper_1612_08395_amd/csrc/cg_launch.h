@@ -29,7 +29,7 @@ inline hipError_t mark(const hipEvent_t* ev, int k, hipStream_t s) {
   return ev ? hipEventRecord(ev[k], s) : hipSuccess;
 }
 
-template <typename T, bool FS>
+template <typename T, int MODE>
 hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int it,
                                const hipEvent_t* ev, hipStream_t s) {
   const int nrp = (g.ny + 1) / 2;
@@ -37,8 +37,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
-    UpdatePro<T, FS, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, up,
+    UpdatePro<T, MODE, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, up,
                        b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
@@ -49,8 +49,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
-    GapEpi<T, FS, PER> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
+    GapEpi<T, MODE, PER> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
                        g.nx, g.ny, K.twx, ge);
     return hipGetLastError();
   });
@@ -59,8 +59,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
-    DirPro<T, FS, PER> dp{b.t, b.g, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, FS, PER>>), dim3(nrp), dim3(NT), 0, s, dp,
+    DirPro<T, MODE, PER> dp{b.t, b.g, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
+    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, dp,
                        b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
   });
@@ -71,8 +71,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
-    DotsEpi<T, PER> de{b.g, b.t, b.sc, b.part, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
+    DotsEpi<T, MODE, PER> de{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
+    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
                        g.nx, g.ny, K.twx, de);
     return hipGetLastError();
   });
@@ -83,15 +83,18 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
 // Queue iterations it0 .. it0 + n - 1.  ev (optional): 6 n + 1 events, the
 // first recorded before the first launch, then six per iteration.
 template <typename T>
-hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b,
-                                bool fixed_set, int it0, int n, const hipEvent_t* ev,
-                                hipStream_t s) {
+hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int mode,
+                                int it0, int n, const hipEvent_t* ev, hipStream_t s) {
   hipError_t e = mark(ev, 0, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < n; ++i) {
     const hipEvent_t* evi = ev ? ev + 1 + 6 * i : nullptr;
-    e = fixed_set ? launch_cg_iteration<T, true>(g, K, b, it0 + i, evi, s)
-                  : launch_cg_iteration<T, false>(g, K, b, it0 + i, evi, s);
+    switch (mode) {
+      case CG_DISP: e = launch_cg_iteration<T, CG_DISP>(g, K, b, it0 + i, evi, s); break;
+      case CG_FIXED: e = launch_cg_iteration<T, CG_FIXED>(g, K, b, it0 + i, evi, s); break;
+      case CG_FORCE: e = launch_cg_iteration<T, CG_FORCE>(g, K, b, it0 + i, evi, s); break;
+      default: return hipErrorInvalidValue;
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -118,13 +121,28 @@ hipError_t launch_prepare(T* t, T* p, const uint8_t* mask, bool clip, size_t n, 
 }
 
 template <typename T>
-hipError_t launch_finalize(const CgBufs<T>& b, bool fixed_set, size_t n, hipStream_t s) {
-  if (fixed_set)
-    hipLaunchKernelGGL((k_finalize<T, true>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p, b.g,
-                       b.mask, b.sc, b.part, n);
+hipError_t launch_finalize(const CgBufs<T>& b, int mode, size_t n, hipStream_t s) {
+  if (mode == CG_FIXED)
+    hipLaunchKernelGGL((k_finalize<T, CG_FIXED>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p,
+                       b.g, b.mask, b.sc, b.part, n);
+  else if (mode == CG_FORCE)
+    hipLaunchKernelGGL((k_finalize<T, CG_FORCE>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p,
+                       b.g, b.mask, b.sc, b.part, n);
   else
-    hipLaunchKernelGGL((k_finalize<T, false>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p, b.g,
-                       b.mask, b.sc, b.part, n);
+    hipLaunchKernelGGL((k_finalize<T, CG_DISP>), dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, b.p,
+                       b.g, b.mask, b.sc, b.part, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_min_h(const double* h, size_t n, CgScal* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_h<T>, dim3(1), dim3(EW_THREADS), 0, s, h, n, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, double v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, p, (T)v, n);
   return hipGetLastError();
 }
 
@@ -156,11 +174,13 @@ hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, s
 
 #define BEM_INSTANTIATE_CG(T)                                                                    \
   template hipError_t launch_cg_iterations<T>(const Geom&, const SpecView<T>&, const CgBufs<T>&, \
-                                              bool, int, int, const hipEvent_t*, hipStream_t);   \
+                                              int, int, int, const hipEvent_t*, hipStream_t);    \
+  template hipError_t launch_fill<T>(T*, double, size_t, hipStream_t);                           \
+  template hipError_t launch_min_h<T>(const double*, size_t, CgScal*, hipStream_t);              \
   template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \
   template hipError_t launch_cold_start<T>(T*, const T*, double, size_t, hipStream_t);           \
   template hipError_t launch_prepare<T>(T*, T*, const uint8_t*, bool, size_t, hipStream_t);      \
-  template hipError_t launch_finalize<T>(const CgBufs<T>&, bool, size_t, hipStream_t);          \
+  template hipError_t launch_finalize<T>(const CgBufs<T>&, int, size_t, hipStream_t);           \
   template hipError_t launch_detach<T>(const CgBufs<T>&, double, size_t, hipStream_t);          \
   template hipError_t launch_to_f64<T>(const T*, double*, size_t, hipStream_t);                  \
   template hipError_t launch_from_f64<T>(const double*, T*, size_t, hipStream_t);                \

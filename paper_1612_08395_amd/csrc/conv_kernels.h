@@ -48,9 +48,10 @@ namespace bem {
 //    make<NTHR>(ya, yb, hasb, nx, va, vb): values to transform (zero for
 //      n >= nx); commit<NTHR>(...): writes back updated state;
 //    finish<NTHR>(red): per-workgroup partial sums.
-//  epilogue (C2R): begin, prefetch<NTHR>(ya, yb, hasb, nx) (issued before
-//    the transform so the loads overlap it), consume<NTHR>(..., va, vb)
-//    with the convolution outputs, finish.
+//  epilogue (C2R): begin (may issue loads of partial sums), prefetch<NTHR>
+//    (ya, yb, hasb, nx) (issued before the transform so the loads overlap
+//    it), ready<NTHR>(red) (reductions the epilogue needs), consume<NTHR>(...,
+//    va, vb) with the convolution outputs, finish.
 template <typename T, int PER>
 struct PlainLoad {
   const T* in;
@@ -92,6 +93,8 @@ struct PlainStore {
   __device__ bool begin(double*) { return true; }
   template <int NTHR>
   __device__ void prefetch(int, int, bool, int) {}
+  template <int NTHR>
+  __device__ void ready(double*) {}
   template <int NTHR>
   __device__ void consume(int ya, int yb, bool hasb, int nx_, const T (&va)[PER],
                           const T (&vb)[PER]) {
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
   // the epilogue's own loads, issued after the spectrum (in-order completion)
   // so that they stay in flight during the transform
   epi.template prefetch<NTHR>(ya, yb, hasb, nx);
+  epi.template ready<NTHR>(red);
 #pragma unroll
   for (int j = 0; j < KPER; ++j) {
     const int k = threadIdx.x + j * NTHR;

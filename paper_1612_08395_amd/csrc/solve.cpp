@@ -36,7 +36,7 @@ struct bem_state_s {
   CgScal* sc_host = nullptr;  // pinned
   bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
   long long device_bytes = 0;
-  int last_iters[2] = {0, 0};  // iterations of the previous CG solve, per mode
+  int last_iters[3] = {0, 0, 0};  // iterations of the previous CG solve, per mode
 };
 
 namespace {
@@ -99,6 +99,7 @@ struct SolveCfg {
   double tol;
   int max_iter;
   int stall_limit;
+  double W = 0.0;  // load control: prescribed sum of p
 };
 
 int status_code(int st) {
@@ -113,13 +114,15 @@ int status_code(int st) {
 // Run one CG solve to convergence on the device.  Returns the status code;
 // *iters receives the iterations of this solve.
 template <typename T>
-int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, double* resid,
+int run_cg(bem_state_s* st, int mode, const SolveCfg& cfg, int* iters, double* resid,
            hipStream_t s) {
+  const bool fixed_set = mode == CG_FIXED;
   CgScal* h = st->sc_host;
   std::memset(h, 0, sizeof(CgScal));
   h->tol = cfg.tol;
   h->max_iter = cfg.max_iter;
   h->stall_limit = cfg.stall_limit;
+  h->W = cfg.W;
   hipError_t e = hipMemcpyAsync(st->sc, h, sizeof(CgScal), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "solver scalars");
   if ((e = launch_prepare<T>((T*)st->t, (T*)st->p, fixed_set ? st->mask : nullptr, !fixed_set,
@@ -130,13 +133,13 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
   const CgBufs<T> b = bufs<T>(st);
   // First chunk sized from the previous solve of this state (warm-started
   // sweeps converge in similar counts), then small doubling chunks.
-  int& last = st->last_iters[fixed_set ? 1 : 0];
+  int& last = st->last_iters[mode];
   int chunk = last > 0 ? std::min(std::max(last + 2, 4), 64) : 4;
   int next = 4;
   int it = 0;
   for (;;) {
     const hipEvent_t* ev = clock_chunk(it, chunk);
-    if ((e = launch_cg_iterations<T>(g, K, b, fixed_set, it, chunk, ev, s)) != hipSuccess)
+    if ((e = launch_cg_iterations<T>(g, K, b, mode, it, chunk, ev, s)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
     it += chunk;
     if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -156,8 +159,8 @@ int run_cg(bem_state_s* st, bool fixed_set, const SolveCfg& cfg, int* iters, dou
 }
 
 template <typename T>
-int finalize(bem_state_s* st, bool fixed_set, hipStream_t s) {
-  hipError_t e = launch_finalize<T>(bufs<T>(st), fixed_set, st->n, s);
+int finalize(bem_state_s* st, int mode, hipStream_t s) {
+  hipError_t e = launch_finalize<T>(bufs<T>(st), mode, st->n, s);
   if (e == hipSuccess) e = hipMemcpyAsync(st->sc_host, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "final sums");
@@ -178,7 +181,7 @@ int apply_import(bem_state_s* st, hipStream_t s) {
   st->pending_import = false;
   st->has_p = true;
   if (!st->import_mask) {
-    int rc = finalize<T>(st, false, s);  // contact set = {p > 0}
+    int rc = finalize<T>(st, CG_DISP, s);  // contact set = {p > 0}
     if (rc) return rc;
   }
   st->has_mask = true;
@@ -211,17 +214,52 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
       if (ee != hipSuccess) return hip_fail(ee, "cold start");
       st->has_p = true;
     }
-    int r = run_cg<T>(st, false, cfg, &it, &resid, s);
+    int r = run_cg<T>(st, CG_DISP, cfg, &it, &resid, s);
     if (r < 0) return r;
     status = worse(status, r);
     iters_total += it;
-    int f = finalize<T>(st, false, s);
+    int f = finalize<T>(st, CG_DISP, s);
     if (f) return f;
     st->has_mask = true;
     return BEM_OK;
   };
 
-  if (!adhesive) {
+  // load control: d unknown (returned as the mean gap shift), hd = h
+  double d_found = P.d;
+  auto force_control = [&](double F) -> int {
+    hipError_t ee = launch_make_hd<T>(h_dev, 0.0, (T*)st->hd, n, s);
+    if (ee != hipSuccess) return hip_fail(ee, "gap profile");
+    if (F == 0.0) {  // no load: no pressure, the surfaces just touch
+      if ((ee = launch_fill<T>((T*)st->p, 0.0, n, s)) != hipSuccess) return hip_fail(ee, "zero load");
+      if ((ee = launch_min_h<T>(h_dev, n, st->sc, s)) != hipSuccess) return hip_fail(ee, "zero load");
+      st->has_p = false;
+      int f = finalize<T>(st, CG_DISP, s);
+      if (f) return f;
+      d_found = st->sc_host->gbar;
+      st->has_mask = true;
+      return BEM_OK;
+    }
+    if (!st->has_p) {  // any positive field: the first iteration scales it to F
+      if ((ee = launch_fill<T>((T*)st->p, 1.0, n, s)) != hipSuccess) return hip_fail(ee, "cold start");
+      st->has_p = true;
+    }
+    SolveCfg fc = cfg;
+    fc.W = F / (K->dx * K->dy);
+    int r = run_cg<T>(st, CG_FORCE, fc, &it, &resid, s);
+    if (r < 0) return r;
+    status = worse(status, r);
+    iters_total += it;
+    int f = finalize<T>(st, CG_FORCE, s);
+    if (f) return f;
+    d_found = st->sc_host->gbar;
+    st->has_mask = true;
+    return BEM_OK;
+  };
+
+  if (P.control == BEM_CTRL_FORCE) {
+    rc = force_control(P.F);
+    if (rc) return rc;
+  } else if (!adhesive) {
     rc = non_adhesive(P.d);
     if (rc) return rc;
   } else {
@@ -232,7 +270,7 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
     if ((e = launch_make_hd<T>(h_dev, P.d, (T*)st->hd, n, s)) != hipSuccess)
       return hip_fail(e, "gap profile");
     for (;;) {
-      int r = run_cg<T>(st, true, cfg, &it, &resid, s);
+      int r = run_cg<T>(st, CG_FIXED, cfg, &it, &resid, s);
       if (r < 0) return r;
       status = worse(status, r);
       iters_total += it;
@@ -249,13 +287,15 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
         break;
       }
     }
-    rc = finalize<T>(st, true, s);
+    rc = finalize<T>(st, CG_FIXED, s);
     if (rc) return rc;
   }
 
   const CgScal* h = st->sc_host;
+  // a solve that ends with no pressure anywhere leaves nothing to warm-start from
+  if (h->fin_contact == 0.0) st->has_p = false;
   if (res) {
-    res->d = P.d;
+    res->d = d_found;
     res->F = K->dx * K->dy * h->fin_sum_p;
     res->n_contact = (long long)h->fin_contact;
     res->area = (double)res->n_contact * K->dx * K->dy;
@@ -286,7 +326,9 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
     if (p_out && !std::is_same<T, double>::value) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "output");
     }
-    if ((e = launch_u_from_gap<T>((const T*)st->g, h_dev, P.d, st->out64, n, s)) != hipSuccess)
+    // load control: g = u + h (no d in it)
+    const double dg = P.control == BEM_CTRL_FORCE ? 0.0 : P.d;
+    if ((e = launch_u_from_gap<T>((const T*)st->g, h_dev, dg, st->out64, n, s)) != hipSuccess)
       return hip_fail(e, "displacement output");
     if ((e = hipMemcpyAsync(u_out, st->out64, n * sizeof(double), kd, s)) != hipSuccess)
       return hip_fail(e, "displacement output");
@@ -344,15 +386,18 @@ int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, 
   if (!P) return set_error(BEM_EINVAL, "bem_solve: params is NULL");
   if (P->precision != BEM_FP64 && P->precision != BEM_MIXED)
     return set_error(BEM_EINVAL, "bem_solve: unknown precision %d", P->precision);
-  if (P->control == BEM_CTRL_FORCE)
-    return set_error(BEM_EUNSUPPORTED, "bem_solve: force control is not implemented");
-  if (P->control != BEM_CTRL_INDENT) return set_error(BEM_EINVAL, "bem_solve: unknown control");
+  if (P->control != BEM_CTRL_INDENT && P->control != BEM_CTRL_FORCE)
+    return set_error(BEM_EINVAL, "bem_solve: unknown control");
   if (!is_finite(P->d)) return set_error(BEM_EINVAL, "bem_solve: non-finite indentation");
+  if (P->control == BEM_CTRL_FORCE && (!is_finite(P->F) || P->F < 0.0))
+    return set_error(BEM_EINVAL, "bem_solve: force control needs a finite force F >= 0");
   if (!is_finite(P->gamma) || P->gamma < 0.0 || !is_finite(P->p_crit) || !is_finite(P->tol) ||
       !is_finite(P->d_preload))
     return set_error(BEM_EINVAL, "bem_solve: invalid adhesion or tolerance parameter");
   *adhesive = P->gamma > 0.0 || P->p_crit > 0.0;
   *pcrit = 0.0;
+  if (*adhesive && P->control == BEM_CTRL_FORCE)
+    return set_error(BEM_EUNSUPPORTED, "bem_solve: force control is for non-adhesive contact");
   if (*adhesive) {
     if (std::fabs(K->dx - K->dy) > 1e-12 * K->dx)
       return set_error(BEM_EUNSUPPORTED,
@@ -458,7 +503,7 @@ int bem_state_reset(bem_state_t st) {
   clear_error();
   if (!st) return set_error(BEM_EINVAL, "bem_state_reset: NULL state");
   st->has_p = st->has_mask = st->pending_import = st->import_mask = false;
-  st->last_iters[0] = st->last_iters[1] = 0;
+  st->last_iters[0] = st->last_iters[1] = st->last_iters[2] = 0;
   return BEM_OK;
 }
 
@@ -539,7 +584,7 @@ int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const d
   if (!K || !h || !prm || !d_list || !res || n_steps < 0)
     return set_error(BEM_EINVAL, "bem_sweep: invalid argument");
   for (int i = 0; i < n_steps; ++i)
-    if (!is_finite(d_list[i])) return set_error(BEM_EINVAL, "bem_sweep: non-finite indentation");
+    if (!is_finite(d_list[i])) return set_error(BEM_EINVAL, "bem_sweep: non-finite step value");
   hipStream_t s = (hipStream_t)stream;
   bem_state_t tmp = nullptr;
   int rc;
@@ -552,7 +597,10 @@ int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const d
   const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
   for (int i = 0; rc == BEM_OK && i < n_steps; ++i) {
     bem_params P = *prm;
-    P.d = d_list[i];
+    if (prm->control == BEM_CTRL_FORCE)
+      P.F = d_list[i];
+    else
+      P.d = d_list[i];
     const bool unloading = adhesive && i > 0 && d_list[i] < d_list[i - 1];
     if (adhesive && !unloading) {
       P.gamma = 0.0;

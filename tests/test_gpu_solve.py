@@ -205,9 +205,12 @@ def test_error_paths():
     announce("errors")
     K = bem.bem_influence_ex(16, 16, 0.1, 0.12, 0.3, 0.3)
     h = np.zeros((16, 16))
-    with pytest.raises(bem.BemError) as e:
-        bem.bem_solve(K, h, bem.bem_params_init(d=0.01, control=bem.BEM_CTRL_FORCE, F=1.0))
+    with pytest.raises(bem.BemError) as e:      # force control is non-adhesive only
+        bem.bem_solve(K, h, bem.bem_params_init(control=bem.BEM_CTRL_FORCE, F=1.0, gamma=1e-3))
     assert e.value.code == bem.BEM_EUNSUPPORTED
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_solve(K, h, bem.bem_params_init(control=bem.BEM_CTRL_FORCE, F=-1.0))
+    assert e.value.code == bem.BEM_EINVAL
     with pytest.raises(bem.BemError) as e:      # adhesion on non-square elements
         bem.bem_solve(K, h, bem.bem_params_init(d=0.01, gamma=1e-3))
     assert e.value.code == bem.BEM_EUNSUPPORTED
