@@ -179,13 +179,15 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
 def big_grid(bem, torch, depths_n=5):
     """4096^2 (8192^2 padded) rough surface, k = -0.3, nu = 0.25, seed 8395,
     same H / q0 / q1 as the 2048^2 workload: mixed-precision indentation
-    sweep to the 10 % height quantile.  Its ~0.75 GB working set exceeds the
-    256 MB last-level cache, so this is the HBM-resident figure."""
+    sweep to the depth below which 64 % of the undeformed gap lies (about
+    10 % contact area, as at d10 of the 2048^2 workload).  Its ~0.75 GB
+    working set exceeds the 256 MB last-level cache, so this is the
+    HBM-resident figure."""
     from paper_1612_08395_amd import inputs
     n = 4096
     two_pi = 2.0 * math.pi / L
     h = inputs.fractal_gap(n, L, H_EXP, Q0 * two_pi, Q1 * two_pi, RMS * L, 8395)
-    dq = float(np.quantile(h, 0.10))
+    dq = float(np.quantile(h, 0.64))
     h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
     K = bem.bem_influence(n, n, L / n, -0.3, 0.25)
     depths = [dq * s / depths_n for s in range(1, depths_n + 1)]
