@@ -129,6 +129,11 @@ def roofline(bem, K, clock, torch):
             traffic = tr.get("bytes_per_launch")
     stream = torch.cuda.current_stream()
     iso = bem.bem_kernel_time(K, bem.BEM_MIXED, 1, reps=50, stream=stream)
+    # the same launches against the usable fp32 vector peak: 4 FFTs of Ly
+    # points per column (5 n log2 n flops each) and the spectrum multiply;
+    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, non-packed fp32
+    flop = Lx * (4 * 5 * Ly * math.log2(Ly) + 4 * Ly)
+    tflops = flop / (ms * 1e-3) / 1e12
     loop = {name: round(clock.ms[k] / max(1, clock.launches[k]) * 1e3, 2)
             for k, name in enumerate(("update_r2c", "column_1", "gap_c2r", "direction_r2c",
                                       "column_2", "dots_c2r"))}
@@ -140,6 +145,8 @@ def roofline(bem, K, clock, torch):
             "timing": "HIP events on the solver stream around each column launch of the "
                       "timed sweeps, launches past convergence excluded",
             "isolated_ms_per_launch": round(iso, 5),
+            "alu_view": {"flop_per_launch": round(flop), "achieved": round(tflops, 2),
+                         "peak": 78.6, "unit": "TFLOP/s", "frac": round(tflops / 78.6, 4)},
             "loop_us_per_launch": loop,
             "loop_us_per_iteration": round(sum(clock.ms) / clock.iterations * 1e3, 2),
             "skipped_launches": clock.skipped,

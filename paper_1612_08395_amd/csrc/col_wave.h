@@ -60,33 +60,48 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   // (4) spectrum multiply; K(ky) is even: K(ky) = K(2 LY - ky)
   if (c != 0) {
     const float* Kc = KT + (size_t)c * kpitch;
+    if constexpr (P == 32) {
+      // lane (k1, h), register r: f = k1 + 32 r + 1024 h, so the folded
+      // index is kq0 + 64 r (h = 0) or kq0 - 64 r (h = 1)
+      const int k1 = lane >> 1, h = lane & 1;
+      int kq = h ? LY - 2 * k1 - parity : 2 * k1 + parity;
+      const int dk = h ? -64 : 64;
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const int ky = 2 * wave_freq<P>(lane, r) + parity;
-      const int kq = ky <= LY ? ky : 2 * LY - ky;
-      v[r] = cscale(v[r], Kc[kq]);
+      for (int r = 0; r < P; ++r) {
+        v[r] = cscale(v[r], Kc[kq]);
+        kq += dk;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int ky = 2 * wave_freq<P>(lane, r) + parity;
+        const int kq = ky <= LY ? ky : 2 * LY - ky;
+        v[r] = cscale(v[r], Kc[kq]);
+      }
     }
   }
   // packed column 0: Z'[k] = ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]); bins
   // k and -k of one parity half sit in different lanes, so swap via the
   // wave's LDS region
   if (c == 0) {
-#pragma unroll
-    for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
-    wave_lds_sync();
     const float* K0 = KT;
     const float* K1 = KT + (size_t)lx * kpitch;
+    {
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const int f = wave_freq<P>(lane, r);
-      const int fp = parity ? (LY - 1 - f) : ((LY - f) & (LY - 1));
-      const cplx<float> z1 = reg[fp];
-      const int ky = 2 * f + parity;
-      const int kq = ky <= LY ? ky : 2 * LY - ky;
-      const float a = 0.5f * (K0[kq] + K1[kq]), b = 0.5f * (K0[kq] - K1[kq]);
-      v[r] = {a * v[r].x + b * z1.x, a * v[r].y - b * z1.y};
+      for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int f = wave_freq<P>(lane, r);
+        const int fp = parity ? (LY - 1 - f) : ((LY - f) & (LY - 1));
+        const cplx<float> z1 = reg[fp];
+        const int ky = 2 * f + parity;
+        const int kq = ky <= LY ? ky : 2 * LY - ky;
+        const float a = 0.5f * (K0[kq] + K1[kq]), b = 0.5f * (K0[kq] - K1[kq]);
+        v[r] = {a * v[r].x + b * z1.x, a * v[r].y - b * z1.y};
+      }
+      wave_lds_sync();
     }
-    wave_lds_sync();
   }
   // (5)
   wave_fft_inv<float, P>(v, reg, twl, lane);

@@ -18,6 +18,8 @@ int col_width_cap() {
   return cap;
 }
 
+// Tuning knob BEM_COL_WAVE: 0 = LDS Stockham column kernel, 1 (default) =
+// wave-FFT kernel.
 int col_wave_enabled() {
   static const int on = [] {
     const char* v = getenv("BEM_COL_WAVE");

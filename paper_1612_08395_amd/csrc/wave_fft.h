@@ -157,15 +157,17 @@ __device__ __forceinline__ void wave_fft_fwd(cplx<T> (&v)[P], cplx<T>* reg,
   wave_lds_sync();
   reg_dft<T, P, -1>(v);
   if constexpr (P == 32) {
-    // lane pair (h = 0: E, h = 1: O): X_lo = E + w O, X_hi = E - w O
+    // lane pair (h = 0: E, h = 1: O): X_lo = E + w O, X_hi = E - w O.  The O
+    // lane multiplies by w before the exchange; each lane then adds (E) or
+    // subtracts (O) its own value from what it receives.
     const bool hi = lane & 1;
     const T sg = hi ? T(-1) : T(1);
 #pragma unroll
     for (int k2 = 0; k2 < 32; ++k2) {
-      const cplx<T> o = {lane_xor1(v[k2].x), lane_xor1(v[k2].y)};
-      const cplx<T> e = hi ? o : v[k2];
-      const cplx<T> wo = mul_wn<T, -1>(hi ? v[k2] : o, k2, 64);
-      v[k2] = {e.x + sg * wo.x, e.y + sg * wo.y};
+      const cplx<T> wv = mul_wn<T, -1>(v[k2], k2, 64);
+      const cplx<T> x = hi ? wv : v[k2];
+      const cplx<T> o = {lane_xor1(x.x), lane_xor1(x.y)};
+      v[k2] = {o.x + sg * x.x, o.y + sg * x.y};
     }
   }
 }
