@@ -185,20 +185,63 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
             "s_per_iter": round(per_iter, 4), "units": oracle_units(cores, Kq)}
 
 
-def big_grid(bem, torch, depths_n=5):
-    """4096^2 (8192^2 padded) rough surface, k = -0.3, nu = 0.25, seed 8395,
-    same H / q0 / q1 as the 2048^2 workload: mixed-precision indentation
-    sweep to the depth below which 64 % of the undeformed gap lies (about
-    10 % contact area, as at d10 of the 2048^2 workload).  Its ~0.75 GB
-    working set exceeds the 256 MB last-level cache, so this is the
-    HBM-resident figure."""
+# Depth of 10 % contact area of the 4096^2 workload, by bisection on the
+# MIXED GPU path (`python bench.py --find-d10-4096`); about 11 max(h): with
+# k = -0.3 the long-range response keeps most of the surfaces apart.
+D10_4096 = 0.0837569479935818
+
+
+def big_grid_setup(bem, torch):
     from paper_1612_08395_amd import inputs
     n = 4096
     two_pi = 2.0 * math.pi / L
     h = inputs.fractal_gap(n, L, H_EXP, Q0 * two_pi, Q1 * two_pi, RMS * L, 8395)
-    dq = float(np.quantile(h, 0.64))
     h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
     K = bem.bem_influence(n, n, L / n, -0.3, 0.25)
+    return n, h_dev, K
+
+
+def find_d10_4096(bem, torch):
+    n, h_dev, K = big_grid_setup(bem, torch)
+    st = bem.bem_state_create(K)
+
+    def area(d):
+        _, res = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=d, precision=bem.BEM_MIXED),
+                                   state=st)
+        frac = res.n_contact / float(n * n)
+        log(f"[d10-4096] d={d:.6e} area={frac:.5f} iters={res.iters}")
+        return frac
+
+    # with k < 0 the long-range response keeps most of the surface apart even
+    # beyond d = max h: widen the bracket until it holds 10 % area
+    lo, hi = 0.0, float(h_dev.max().item())
+    for _ in range(12):
+        if area(hi) >= AREA_FRAC:
+            break
+        lo, hi = hi, 2.0 * hi
+    d = 0.5 * (lo + hi)
+    for _ in range(40):
+        d = 0.5 * (lo + hi)
+        frac = area(d)
+        if abs(frac - AREA_FRAC) <= 0.01 * AREA_FRAC:
+            break
+        if frac < AREA_FRAC:
+            lo = d
+        else:
+            hi = d
+    st.free()
+    K.free()
+    return d
+
+
+def big_grid(bem, torch, depths_n=5):
+    """4096^2 (8192^2 padded) rough surface, k = -0.3, nu = 0.25, seed 8395,
+    same H / q0 / q1 as the 2048^2 workload: mixed-precision indentation
+    sweep of 5 depths up to D10_4096 (10 % contact area).  Its ~0.75 GB
+    working set exceeds the 256 MB last-level cache, so this is the
+    HBM-resident figure."""
+    n, h_dev, K = big_grid_setup(bem, torch)
+    dq = D10_4096 if D10_4096 is not None else find_d10_4096(bem, torch)
     depths = [dq * s / depths_n for s in range(1, depths_n + 1)]
 
     def sweep():
@@ -324,6 +367,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests per serving run (0: skip the serving measurement)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--find-d10-4096", action="store_true")
     ap.add_argument("--no-big-grid", action="store_true",
                     help="skip the 4096^2 (HBM-resident) mixed sweep")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -340,6 +384,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_kernels:
         return profile_kernels(bem, torch)
+    if args.find_d10_4096:
+        print(json.dumps({"d10_4096": find_d10_4096(bem, torch)}), flush=True)
+        return 0
     log("[bench] building workload")
     h = workload()
     h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")

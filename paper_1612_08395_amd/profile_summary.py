@@ -91,7 +91,8 @@ def trace(args):
             b = json.loads([ln for ln in fh if ln.startswith("{")][-1])
         r = b["roofline"]
         out += ["", f"The same run's bench.py line (HIP events on the solver stream around "
-                f"each column launch of its timed sweeps): {r['ms_per_launch'] * 1e3:.2f} us per "
+                f"each column launch of one sweep of the timed workload): "
+                f"{r['ms_per_launch'] * 1e3:.2f} us per "
                 f"launch over {r['launches_timed']} launches, {r['achieved']} GB/s algorithmic "
                 f"({r['frac']} of {r['peak']} GB/s); trace mean of working launches "
                 f"{focus['avg_us_working']:.2f} us.  The event figure includes the dispatch gap "
