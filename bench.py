@@ -110,7 +110,8 @@ def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
 
 def roofline(bem, K, clock, torch):
     """Dominant kernel: the fused column sweep (FFT x spectrum x IFFT), FP32,
-    launched twice per CG iteration.  Algorithmic bytes per launch: read +
+    launched once per CG iteration (the second convolution's column kernel,
+    transform + spectral inner product, is reported beside it).  Algorithmic bytes per launch: read +
     write the ny x Lx complex row spectrum and read the (Lx+1) x (Ly+1) real
     kernel spectrum.  Duration: the solver clock's mean over every column
     launch that did work in one sweep of the timed workload (HIP events on
@@ -118,8 +119,8 @@ def roofline(bem, K, clock, torch):
     info = K.info
     Lx, Ly = info.Mx // 2, info.My // 2
     bytes_per_launch = 2 * info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
-    n_col = clock.launches[1] + clock.launches[4]
-    ms = (clock.ms[1] + clock.ms[4]) / n_col
+    n_col = clock.launches[1]
+    ms = clock.ms[1] / n_col
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -136,8 +137,11 @@ def roofline(bem, K, clock, torch):
     flop = Lx * (4 * 5 * Ly * math.log2(Ly) + 4 * Ly)
     tflops = flop / (ms * 1e-3) / 1e12
     loop = {name: round(clock.ms[k] / max(1, clock.launches[k]) * 1e3, 2)
-            for k, name in enumerate(("update_r2c", "column_1", "gap_c2r", "direction_r2c",
-                                      "column_2", "dots_c2r"))}
+            for k, name in enumerate(("update_r2c", "column_conv", "gap_c2r", "direction_r2c",
+                                      "column_energy", "none_event_gap"))}
+    # second convolution's column kernel: reads S and the spectrum quarter
+    e_bytes = info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
+    e_ms = clock.ms[4] / max(1, clock.launches[4])
     return {"bound": "hbm", "kernel": "k_col_conv_w<2048,4> (column sweep, FP32)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -150,6 +154,8 @@ def roofline(bem, K, clock, torch):
             "alu_view": {"flop_per_launch": round(flop), "achieved": round(tflops, 2),
                          "peak": 78.6, "unit": "TFLOP/s", "frac": round(tflops / 78.6, 4)},
             "loop_us_per_launch": loop,
+            "column_energy": {"ms_per_launch": round(e_ms, 5), "algorithmic_bytes_per_launch":
+                              e_bytes, "GBps": round(e_bytes / (e_ms * 1e-3) / 1e9, 1)},
             "loop_us_per_iteration": round(sum(clock.ms) / clock.iterations * 1e3, 2),
             "skipped_launches": clock.skipped,
             "skipped_us_total": round(clock.skipped_ms * 1e3, 1)}
@@ -266,14 +272,13 @@ def big_grid(bem, torch, depths_n=5):
     clk = bem.bem_clock_stop()
     K.free()
     iters = sum(r["iters"] for r in res)
-    n_col = clk.launches[1] + clk.launches[4]
-    col_ms = (clk.ms[1] + clk.ms[4]) / n_col
+    col_ms = clk.ms[1] / clk.launches[1]
     col_bytes = 2 * n * n * 8 + (n + 1) * (n + 1) * 4
     return {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395,
             "depths": depths_n, "d_max": dq, "solves_per_s": round(depths_n / t, 3),
             "iters_per_solve": round(iters / depths_n, 2),
             "loop_us_per_iteration": round(sum(clk.ms) / clk.iterations * 1e3, 2),
-            "loop_GBps_algorithmic": round(124.0 * n * n * iters / t / 1e9, 1),
+            "loop_GBps_algorithmic": round(100.0 * n * n * iters / t / 1e9, 1),
             "column_us_per_launch": round(col_ms * 1e3, 2),
             "column_GBps_algorithmic": round(col_bytes / (col_ms * 1e-3) / 1e9, 1),
             "contact_area_final": res[-1]["n_contact"] / float(n * n)}
@@ -418,10 +423,10 @@ def main():
     solves32 = N_DEPTHS * args.steps / t32
     solves64 = N_DEPTHS * args.fp64_steps / t64
     ms_step = t32 / args.steps * 1e3
-    # whole-loop effective bandwidth: 124 algorithmic bytes per element per CG
-    # iteration (FP32 path, fused design), 248 for FP64
-    loop32 = 124.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
-    loop64 = 248.0 * N * N * sum(it64) / (t64 / args.fp64_steps) / 1e9
+    # whole-loop effective bandwidth: 100 algorithmic bytes per element per CG
+    # iteration (FP32 path, five launches), 200 for FP64
+    loop32 = 100.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
+    loop64 = 200.0 * N * N * sum(it64) / (t64 / args.fp64_steps) / 1e9
 
     log("[bench] roofline")
     roof = roofline(bem, K, clk32, torch)
@@ -440,8 +445,7 @@ def main():
                  "ms_per_step": round(t64 / args.fp64_steps * 1e3, 3),
                  "iters_per_solve": round(sum(it64) / len(it64), 2),
                  "loop_GBps_algorithmic": round(loop64, 1),
-                 "column_us_per_launch": round((clk64.ms[1] + clk64.ms[4]) /
-                                               (clk64.launches[1] + clk64.launches[4]) * 1e3, 2)},
+                 "column_us_per_launch": round(clk64.ms[1] / clk64.launches[1] * 1e3, 2)},
         "iters_per_solve": round(sum(it32) / len(it32), 2),
         "loop_GBps_algorithmic": round(loop32, 1),
         "mixed_vs_fp64": {"rel_l2_pressure_per_depth": [float(f"{e:.3e}") for e in err],
@@ -449,9 +453,10 @@ def main():
                           "status_mixed": sorted({x["status"] for x in res32[-1]})},
         "contact_area_final": res32[-1][-1]["n_contact"] / float(N * N),
     }
-    # compulsory traffic: each convolution reads its input and the kernel
-    # spectrum quarter and writes its output (12 B per element in FP32)
-    comp = 24.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
+    # compulsory traffic: the first convolution reads its input and the kernel
+    # spectrum quarter and writes its output (12 B per element in FP32), the
+    # second (an inner product) reads its input and the spectrum (8 B)
+    comp = 20.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
     out["compulsory_GBps"] = round(comp, 1)
     out["compulsory_frac"] = round(comp / HBM_PEAK_GBS, 4)
     if not args.no_big_grid:

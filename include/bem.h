@@ -294,7 +294,8 @@ int bem_server_free(bem_server_t srv);
  * events on `stream`) of `reps` back-to-back launches of one sweep of the
  * convolution of Eq. 13 on the handle's grid: which = 0 row R2C transform,
  * 1 column transform x kernel spectrum x inverse transform, 2 row C2R
- * transform.  Runs on a zero field in the handle's scratch buffers (same
+ * transform, 3 column transform and spectral energy sum_k Khat |T|^2 (the
+ * solver's second convolution, which only needs that inner product).  Runs on a zero field in the handle's scratch buffers (same
  * kernels and launch shapes as the solver's sweeps).  Synchronises `stream`.
  */
 int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void* stream,
@@ -302,10 +303,13 @@ int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void*
 
 /*
  * Solver clock -- measurement hook for the conjugate-gradient loop of the
- * contact solve (Section 2.2, Polonsky-Keer iteration; each iteration is two
- * convolutions of Eq. 13, i.e. six kernel launches:
+ * contact solve (Section 2.2, Polonsky-Keer iteration).  Each iteration is
+ * reported as six launch kinds:
  *   0 pressure update + row R2C,  1 column sweep,  2 row C2R + gap,
- *   3 direction + row R2C,        4 column sweep,  5 row C2R + dot products).
+ *   3 direction + row R2C,        4 column transform of the direction with
+ *   the spectral inner product sum t (C K * t)  (force control: full column
+ *   sweep),  5 row C2R + dot products (force control only; otherwise no
+ *   launch and a zero-length interval).
  * After bem_clock_start, every bem_solve / bem_solve_dev / bem_sweep made BY
  * THE CALLING THREAD records a HIP event on its solver stream before the
  * first launch of each queued chunk and after every launch; no extra host

@@ -187,8 +187,8 @@ int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void*
   if (!K || !avg_ms) return set_error(BEM_EINVAL, "bem_kernel_time: NULL argument");
   if (precision != BEM_FP64 && precision != BEM_MIXED)
     return set_error(BEM_EINVAL, "bem_kernel_time: unknown precision %d", precision);
-  if (which < 0 || which > 2 || reps < 1)
-    return set_error(BEM_EINVAL, "bem_kernel_time: which in {0,1,2}, reps >= 1");
+  if (which < 0 || which > 3 || reps < 1)
+    return set_error(BEM_EINVAL, "bem_kernel_time: which in {0,1,2,3}, reps >= 1");
   return sweep_time(K, precision, which, reps, (hipStream_t)stream, avg_ms);
 }
 

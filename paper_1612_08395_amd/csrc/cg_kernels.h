@@ -27,10 +27,16 @@
 //   K1 row R2C   prologue UpdatePro : update p from the previous tau, t, g
 //   K2 column    (fused spectrum multiply)
 //   K3 row C2R   epilogue GapEpi    : g = u + (h - d), sums for G
-//   K4 row R2C   prologue DirPro    : convergence decision, new direction t
-//   K5 column
-//   K6 row C2R   epilogue DotsEpi   : sum g t, sum r t (r is not stored)
-// Since t = 0 off Ic, the sums of K6 need no mask.
+//   K4 row R2C   prologue DirPro    : convergence decision, new direction t,
+//                                     sum g t
+//   K5 column    forward transform and sum_k KT |T|^2 = sum t r (Parseval;
+//                t is zero outside the grid), no inverse transforms
+// r = C K * t enters only through tau, so the second convolution ends in the
+// spectral domain: five launches per iteration.  Since t = 0 off Ic, the
+// sums need no mask.  Load control needs the mean of r over Ic and keeps the
+// sixth launch:
+//   K5 column    (full, as K2)
+//   K6 row C2R   epilogue DotsEpi   : sum g t, sum r t, sum t, sum_Ic r
 //
 // Reductions are FP64 and the iteration kernels use no atomics or fences:
 // every reducing kernel writes one partial per workgroup (fixed-order block
@@ -78,9 +84,11 @@ constexpr int kPartUpd = 0;                      // 3 values: sum|dp|, sum|p|, n
 constexpr int kPartGap = 3 * kMaxRowBlocks;      // 2 values: sum_Ic g^2, sum_Ic (h-d)^2
                                                  // load control, 4: sum_Ic e, sum_Ic e^2,
                                                  // |Ic|, sum_Ic u^2 (e = g - previous gbar)
-constexpr int kPartDots = 7 * kMaxRowBlocks;     // 2 values: sum g t, sum r t; load
-                                                 // control, 4: + sum t, sum_Ic r
-constexpr int kPartElem = 11 * kMaxRowBlocks;    // elementwise kernels (3 values x 1024)
+constexpr int kPartDots = 7 * kMaxRowBlocks;     // 1 value: sum g t (K4); load control,
+                                                 // 4 (K6): sum g t, sum r t, sum t, sum_Ic r
+constexpr int kMaxColBlocks = 4096;
+constexpr int kPartRT = 11 * kMaxRowBlocks;      // 1 value per column workgroup: sum t r
+constexpr int kPartElem = kPartRT + kMaxColBlocks;   // elementwise kernels (3 values x 1024)
 constexpr int kPartTotal = kPartElem + 3 * 1024;
 
 // Block sums of NV values (result in every thread), one barrier pair.
@@ -201,7 +209,7 @@ __device__ __forceinline__ bool grid_reduce_last(const double (&acc)[NV], double
 template <typename T, int MODE, int PER>
 struct UpdatePro {
   static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
-  static constexpr int NVD = FC ? 4 : 2;
+  static constexpr int NVD = FC ? 4 : 1;
   T* p;
   const T* t;
   const T* g;
@@ -209,17 +217,20 @@ struct UpdatePro {
   const CgScal* sc;
   double* part;
   int nx, nb, it;
+  int nbc;               // column workgroups of K5 (sum t r partials)
   double tau, a_dp, a_p, a_ol;
   double sprev, gshift;  // load control: scale of the stored p, mean gap
   T pa[PER], pb[PER], ta[PER], tb[PER], ga[PER], gb[PER];
   bool ma[PER], mb[PER];
   Partials<NVD> dots;
+  Partials<1> rts;
   template <int NTHR>
   __device__ bool issue() {
     if (sc->done) return false;
-    // always issued (a valid buffer; unused when it == 0) so that no branch
+    // always issued (valid buffers; unused when it == 0) so that no branch
     // separates these loads from the field loads
     dots.template issue<NTHR>(part + kPartDots, nb);
+    if constexpr (!FC) rts.template issue<NTHR>(part + kPartRT, nbc);
     return true;
   }
   template <int NTHR>
@@ -260,9 +271,11 @@ struct UpdatePro {
       const double den = tot[1] - (nc > 0.0 ? tot[3] / nc : 0.0) * tot[2];
       tau = (it > 0 && den != 0.0) ? tot[0] / den : 0.0;
     } else {
+      double rt[1];
+      rts.template total<NTHR>(part + kPartRT, nbc, red, rt);
       sprev = 1.0;
       gshift = 0.0;
-      tau = (it > 0 && tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
+      tau = (it > 0 && rt[0] != 0.0) ? tot[0] / rt[0] : 0.0;
     }
     return true;
   }
@@ -432,7 +445,7 @@ struct DirPro {
   CgScal* sc;
   double* part;
   int nx, nb, it;
-  double ratio, gbar;
+  double ratio, gbar, a_gt;
   T ga[PER], gb[PER], ta[PER], tb[PER];
   bool ca[PER], cb[PER];
   Partials<3> pu;
@@ -533,11 +546,15 @@ struct DirPro {
   }
   template <int NTHR>
   __device__ void make(int, int, bool, int, T (&va)[PER], T (&vb)[PER]) {
+    double gt = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       va[q] = ca[q] ? (T)((double)ga[q] - gbar + ratio * (double)ta[q]) : T(0);
       vb[q] = cb[q] ? (T)((double)gb[q] - gbar + ratio * (double)tb[q]) : T(0);
+      // sum g t with the stored (rounded) t; t = 0 off Ic
+      gt += (double)ga[q] * (double)va[q] + (double)gb[q] * (double)vb[q];
     }
+    a_gt = gt;
   }
   template <int NTHR>
   __device__ void commit(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
@@ -552,10 +569,15 @@ struct DirPro {
     }
   }
   template <int NTHR>
-  __device__ void finish(double*) {}
+  __device__ void finish(double* red) {
+    if constexpr (!FC) {
+      double acc[1] = {a_gt};
+      write_partials<1, NTHR>(acc, red, part + kPartDots);
+    }
+  }
 };
 
-// K6 epilogue: sum g t and sum r t (t = 0 off Ic, so no mask is needed).
+// K6 epilogue (load control only): sum g t and sum r t (t = 0 off Ic, so no mask is needed).
 // Load control: g is shifted by gbar, and sum t, sum_Ic r (Ic = {p > 0})
 // give the shift of r by its mean over Ic.
 template <typename T, int MODE, int PER>

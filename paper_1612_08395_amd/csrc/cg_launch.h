@@ -37,7 +37,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     constexpr int L = decltype(LX)::value;
     constexpr int NT = row_threads(L);
     constexpr int PER = row_per<L, NT>();
-    UpdatePro<T, MODE, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it};
+    UpdatePro<T, MODE, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it,
+                               col_energy_blocks<T>(g)};
     hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, up,
                        b.S, g.nx, g.ny, K.twx);
     return hipGetLastError();
@@ -65,19 +66,28 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     return hipGetLastError();
   });
   if (e != hipSuccess || (e = mark(ev, 3, s)) != hipSuccess) return e;
-  if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
-  if ((e = mark(ev, 4, s)) != hipSuccess) return e;
-  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    DotsEpi<T, MODE, PER> de{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
-                       g.nx, g.ny, K.twx, de);
-    return hipGetLastError();
-  });
-  if (e != hipSuccess) return e;
-  return mark(ev, 5, s);
+  if constexpr (MODE != CG_FORCE) {
+    // second convolution: only sum t (C K * t) is needed (Parseval); no
+    // inverse transforms and no sixth launch (its event follows at once)
+    if ((e = launch_col_energy<T>(g, K, b.S, &b.sc->done, b.part + kPartRT, s)) != hipSuccess)
+      return e;
+    if ((e = mark(ev, 4, s)) != hipSuccess) return e;
+    return mark(ev, 5, s);
+  } else {
+    if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
+    if ((e = mark(ev, 4, s)) != hipSuccess) return e;
+    e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
+      constexpr int L = decltype(LX)::value;
+      constexpr int NT = row_threads(L);
+      constexpr int PER = row_per<L, NT>();
+      DotsEpi<T, MODE, PER> de{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
+      hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s,
+                         b.S, g.nx, g.ny, K.twx, de);
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return mark(ev, 5, s);
+  }
 }
 
 // Queue iterations it0 .. it0 + n - 1.  ev (optional): 6 n + 1 events, the

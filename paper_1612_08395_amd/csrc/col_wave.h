@@ -125,3 +125,86 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
 }
 
 }  // namespace bem
+
+namespace bem {
+
+// Forward wave-FFT column transform and the spectral energy
+// sum_k KT(k) |T(k)|^2 (see k_col_energy): the first half of k_col_conv_w,
+// then, per register, the weight of its frequency instead of the multiply.
+// One FP64 partial per workgroup into part[blockIdx.x].
+template <int LY, int NC>
+__global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __restrict__ S,
+                                                           int lx, int ny,
+                                                           const float* __restrict__ KT,
+                                                           int kpitch,
+                                                           const cplx<float>* __restrict__ tw,
+                                                           const cplx<float>* __restrict__ twl,
+                                                           const int* __restrict__ done,
+                                                           double* __restrict__ part) {
+  constexpr int P = LY / 64;
+  constexpr int REG = wave_region<P>();
+  constexpr int NT = 128 * NC;
+  __shared__ cplx<float> lds[2 * NC * REG];
+  __shared__ double red[NT / 64];
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jc = wv >> 1, parity = wv & 1;
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC;
+  const int c = c0 + jc;
+  cplx<float>* reg = lds + wv * REG;
+  for (int f = threadIdx.x; f < NC * LY; f += NT) {
+    const int cc = f % NC, n = f / NC;
+    cplx<float> x = {0.f, 0.f};
+    if (n < ny) x = S[(size_t)n * lx + c0 + cc];
+    lds[(2 * cc) * REG + n] = x;
+  }
+  __syncthreads();
+  cplx<float> v[P];
+  const cplx<float>* src = lds + (2 * jc) * REG;
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = src[lane + 64 * m];
+  __syncthreads();
+  if (parity) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = cmul(v[m], tw[lane + 64 * m]);
+  }
+  wave_fft_fwd<float, P>(v, reg, twl, lane);
+  double e = 0.0;
+  if (c != 0) {
+    const float* Kc = KT + (size_t)c * kpitch;
+    if constexpr (P == 32) {
+      const int k1 = lane >> 1, h = lane & 1;
+      int kq = h ? LY - 2 * k1 - parity : 2 * k1 + parity;
+      const int dk = h ? -64 : 64;
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        e += energy_term(v[r], Kc[kq]);
+        kq += dk;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int ky = 2 * wave_freq<P>(lane, r) + parity;
+        e += energy_term(v[r], Kc[ky <= LY ? ky : 2 * LY - ky]);
+      }
+    }
+  } else {
+    // packed column 0: the partner bin -ky sits in another lane
+#pragma unroll
+    for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
+    wave_lds_sync();
+    const float* K1 = KT + (size_t)lx * kpitch;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int f = wave_freq<P>(lane, r);
+      const cplx<float> zm = reg[parity ? (LY - 1 - f) : ((LY - f) & (LY - 1))];
+      const int ky = 2 * f + parity;
+      const int kq = ky <= LY ? ky : 2 * LY - ky;
+      e += energy_packed(v[r], zm, KT[kq], K1[kq]);
+    }
+  }
+  e = block_sum<NT>(e, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
+}  // namespace bem

@@ -119,6 +119,52 @@ hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T*
   });
 }
 
+// The wave kernel for FP32 at Ly = 2048 (4 columns per workgroup), else the
+// LDS Stockham kernel with the column width launch_col uses.
+template <typename T>
+static bool energy_wave(const Geom& g) {
+  return std::is_same<T, float>::value && col_wave_enabled() && g.Ly == 2048 && g.Lx % 4 == 0;
+}
+
+template <typename T>
+int col_energy_blocks(const Geom& g) {
+  return energy_wave<T>(g) ? g.Lx / 4 : g.Lx / col_width<T>(g.Ly, g.Lx);
+}
+
+template <typename T>
+hipError_t launch_col_energy(const Geom& g, const SpecView<T>& K, const cplx<T>* S,
+                             const int* done, double* part, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (energy_wave<T>(g)) {
+      hipLaunchKernelGGL((k_col_energy_w<2048, 4>), dim3(g.Lx / 4), dim3(512), 0, s, S, g.Lx, g.ny,
+                         K.KT, g.kpitch, K.twy, K.twly, done, part);
+      return hipGetLastError();
+    }
+  }
+  const int W = col_width<T>(g.Ly, g.Lx);
+  return dispatch_L(g.Ly, [&](auto LYc) -> hipError_t {
+    constexpr int LY = decltype(LYc)::value;
+    return dispatch_W(W, [&](auto Wc) -> hipError_t {
+      constexpr int WW = decltype(Wc)::value;
+      if constexpr (WW > col_width_lds<T>(LY)) {
+        return hipErrorInvalidValue;
+      } else {
+        constexpr int NT = col_threads(WW, LY);
+        hipLaunchKernelGGL((k_col_energy<T, LY, WW, NT>), dim3(g.Lx / WW), dim3(NT), 0, s, S,
+                           g.Lx, g.ny, K.KT, g.kpitch, K.twy, done, part);
+        return hipGetLastError();
+      }
+    });
+  });
+}
+
+template int col_energy_blocks<float>(const Geom&);
+template int col_energy_blocks<double>(const Geom&);
+template hipError_t launch_col_energy<float>(const Geom&, const SpecView<float>&,
+                                             const cplx<float>*, const int*, double*, hipStream_t);
+template hipError_t launch_col_energy<double>(const Geom&, const SpecView<double>&,
+                                              const cplx<double>*, const int*, double*,
+                                              hipStream_t);
 template hipError_t launch_sweep<float>(const Geom&, const SpecView<float>&, int, const float*,
                                         float*, cplx<float>*, hipStream_t);
 template hipError_t launch_sweep<double>(const Geom&, const SpecView<double>&, int, const double*,

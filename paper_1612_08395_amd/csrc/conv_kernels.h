@@ -252,6 +252,72 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
   }
 }
 
+// Spectral energy of the packed half spectrum.  After the forward column
+// transform, the full padded spectrum T(kx, ky) of a real field is known from
+// columns kx = 1 .. Lx-1 (each also stands for Mx - kx) and from the packed
+// column 0, whose transform is Z = A + i B with A (kx = 0) and B (kx = Lx)
+// Hermitian in ky: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i.
+// Returns sum_k KT(k) |T(k)|^2 for this thread's share.
+template <typename T>
+__device__ __forceinline__ double energy_term(cplx<T> z, T kt) {
+  return 2.0 * (double)kt * ((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+}
+template <typename T>
+__device__ __forceinline__ double energy_packed(cplx<T> z, cplx<T> zm, T k0, T k1) {
+  const double ax = 0.5 * ((double)z.x + (double)zm.x), ay = 0.5 * ((double)z.y - (double)zm.y);
+  const double bx = 0.5 * ((double)z.y + (double)zm.y), by = 0.5 * ((double)zm.x - (double)z.x);
+  return (double)k0 * (ax * ax + ay * ay) + (double)k1 * (bx * bx + by * by);
+}
+
+// Forward column transform and the spectral energy sum_k KT(k) |T(k)|^2.
+// With KT = C Khat / (Mx My), Parseval gives sum_x t(x) (C K * t)(x) for
+// the zero-padded field t whose row spectrum is S; so this replaces the
+// inverse transforms of a convolution whose only use is that inner product.
+// One FP64 partial per workgroup into part[blockIdx.x].
+template <typename T, int LY, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__ S, int lx, int ny,
+                                                     const T* __restrict__ KT, int kpitch,
+                                                     const cplx<T>* __restrict__ tw,
+                                                     const int* __restrict__ done,
+                                                     double* __restrict__ part) {
+  if (done && *done) return;
+  constexpr int STR = lds_len(LY);
+  __shared__ cplx<T> lds[2 * W * STR];
+  __shared__ double red[64];
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
+  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
+    const int c = f % W, n = f / W;
+    cplx<T> x = {T(0), T(0)};
+    if (n < ny) x = S[(size_t)n * lx + c0 + c];
+    lds[(2 * c) * STR + lds_pad(n)] = x;
+    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  }
+  __syncthreads();
+  fft_lds<T, LY, -1, 2 * W, NTHR, STR>(lds, tw);
+  double e = 0.0;
+  for (int f = threadIdx.x; f < 2 * W * LY; f += NTHR) {
+    const int s = f / LY, kp = f % LY;
+    const int c = s >> 1;
+    if (c0 + c == 0) continue;
+    const int ky = 2 * kp + (s & 1);
+    const int kq = ky <= LY ? ky : 2 * LY - ky;
+    e += energy_term(lds[s * STR + lds_pad(kp)], KT[(size_t)(c0 + c) * kpitch + kq]);
+  }
+  if (c0 == 0) {
+    // column 0: sequences 0 (even ky) and 1 (odd ky); partner of ky is -ky
+    for (int f = threadIdx.x; f < 2 * LY; f += NTHR) {
+      const int s = f / LY, kp = f % LY;
+      const int kpp = s ? LY - 1 - kp : (LY - kp) & (LY - 1);
+      const int ky = 2 * kp + s;
+      const int kq = ky <= LY ? ky : 2 * LY - ky;
+      e += energy_packed(lds[s * STR + lds_pad(kp)], lds[s * STR + lds_pad(kpp)], KT[kq],
+                         KT[(size_t)lx * kpitch + kq]);
+    }
+  }
+  e = block_sum<NTHR>(e, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
 template <typename T, int L, int NTHR, class Epi>
 __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
                                                   const cplx<T>* __restrict__ tw, Epi epi_arg) {

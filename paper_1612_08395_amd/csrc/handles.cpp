@@ -71,7 +71,7 @@ int influence_build(bem_influence_s* h) {
 
 void influence_release(bem_influence_s* h) {
   void* ptrs[] = {h->Kq, h->KT64, h->KT32, h->twx64, h->twy64, h->twx32, h->twy32,
-                  h->twly64, h->twly32, h->S64, h->S32, h->io64, h->io32};
+                  h->twly64, h->twly32, h->S64, h->S32, h->io64, h->io32, h->epart};
   for (void* p : ptrs)
     if (p) hipFree(p);
   h->device_bytes = 0;
@@ -125,6 +125,9 @@ int sweep_time(bem_influence_s* h, int precision, int which, int reps, hipStream
     if (e == hipSuccess) e = hipMemsetAsync(h->S32, 0, ns * sizeof(cplx<float>), s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel timing setup");
+  if (which == 3 && !h->epart &&
+      (rc = dev_alloc(h, (void**)&h->epart, 4096 * sizeof(double), "scratch")))
+    return rc;
   hipEvent_t a, b;
   if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "event");
   if ((e = hipEventCreate(&b)) != hipSuccess) {
@@ -135,9 +138,14 @@ int sweep_time(bem_influence_s* h, int precision, int which, int reps, hipStream
   for (int r = -1; r < reps && e == hipSuccess; ++r) {
     if (r == 0) e = hipEventRecord(a, s);
     if (e != hipSuccess) break;
-    e = precision == BEM_FP64
-            ? launch_sweep<double>(h->g, spec_view<double>(h), which, h->io64, h->io64, h->S64, s)
-            : launch_sweep<float>(h->g, spec_view<float>(h), which, h->io32, h->io32, h->S32, s);
+    if (which == 3)
+      e = precision == BEM_FP64
+              ? launch_col_energy<double>(h->g, spec_view<double>(h), h->S64, nullptr, h->epart, s)
+              : launch_col_energy<float>(h->g, spec_view<float>(h), h->S32, nullptr, h->epart, s);
+    else
+      e = precision == BEM_FP64
+              ? launch_sweep<double>(h->g, spec_view<double>(h), which, h->io64, h->io64, h->S64, s)
+              : launch_sweep<float>(h->g, spec_view<float>(h), which, h->io32, h->io32, h->S32, s);
   }
   if (e == hipSuccess) e = hipEventRecord(b, s);
   if (e == hipSuccess) e = hipEventSynchronize(b);

@@ -28,6 +28,7 @@ struct bem_influence_s {
   bem::cplx<float>* S32 = nullptr;
   double* io64 = nullptr;
   float* io32 = nullptr;
+  double* epart = nullptr;   // partials of the spectral-energy sweep (timing hook)
 };
 
 namespace bem {
@@ -35,6 +36,9 @@ namespace bem {
 int set_error(int code, const char* fmt, ...);
 void clear_error();
 int hip_fail(hipError_t e, const char* what);
+
+// Bytes of a solver state's partial-sum buffer (solve.cpp; footprint model).
+long long state_partial_bytes();
 
 // Solver clock (clock.cpp): events for a chunk of n CG iterations starting at
 // it0 (nullptr when the calling thread's clock is off), and the outcome of

@@ -100,7 +100,16 @@ template <typename T>
 hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int* done,
                       hipStream_t s);
 
-// One sweep of the convolution on its own: 0 row R2C, 1 column, 2 row C2R.
+// Forward column transform and spectral energy sum_k KT |T|^2 (one FP64
+// partial per workgroup into part); col_energy_blocks gives how many.
+template <typename T>
+int col_energy_blocks(const Geom& g);
+template <typename T>
+hipError_t launch_col_energy(const Geom& g, const SpecView<T>& K, const cplx<T>* S,
+                             const int* done, double* part, hipStream_t s);
+
+// One sweep of the convolution on its own: 0 row R2C, 1 column, 2 row C2R,
+// 3 column transform + spectral energy.
 template <typename T>
 hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T* p, T* u,
                         cplx<T>* S, hipStream_t s);

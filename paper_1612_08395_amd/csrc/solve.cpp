@@ -42,6 +42,13 @@ struct bem_state_s {
 namespace {
 
 constexpr int kPartials = kPartTotal;
+}  // namespace
+
+namespace bem {
+long long state_partial_bytes() { return (long long)kPartials * sizeof(double); }
+}  // namespace bem
+
+namespace {
 
 int salloc(bem_state_s* st, void** p, size_t bytes, const char* what) {
   hipError_t e = hipMalloc(p, bytes);
