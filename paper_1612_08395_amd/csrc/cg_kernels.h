@@ -22,8 +22,8 @@
 // same s on reading.  G = sum_Ic (g - gbar)^2 is formed from sums shifted by
 // the previous gbar, which keeps the subtraction benign near convergence.
 //
-// One iteration is six kernel launches; the vector work is fused into the
-// row sweeps of the two convolutions:
+// One iteration is five kernel launches (six under load control); the
+// vector work is fused into the row sweeps of the two convolutions:
 //   K1 row R2C   prologue UpdatePro : update p from the previous tau, t, g
 //   K2 column    (fused spectrum multiply)
 //   K3 row C2R   epilogue GapEpi    : g = u + (h - d), sums for G
