@@ -2,8 +2,8 @@
 // adhesive detach / re-solve loop (Section 3.1), sweeps, Eq. 24.
 //
 // The host never takes part in an iteration: it queues a chunk of CG
-// iterations (five kernels each, six under force control), copies the 200-byte scalar block back and
-// looks at the device-side `done` flag.  Kernels queued after convergence
+// iterations (five kernels each, six under force control), copies the
+// scalar block back and looks at the device-side `done` flag.  Kernels queued after convergence
 // return at once, so results do not depend on the chunking.
 #include <hip/hip_runtime.h>
 
