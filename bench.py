@@ -379,6 +379,8 @@ def main():
                     help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
                          "and a 1 GiB device copy, for hardware-counter runs")
     args = ap.parse_args()
+    if args.steps < 1 or args.fp64_steps < 1 or args.warmup < 0:
+        ap.error("--steps and --fp64-steps must be >= 1, --warmup >= 0")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)

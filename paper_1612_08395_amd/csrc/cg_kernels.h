@@ -141,10 +141,10 @@ __device__ __forceinline__ void read_totals(const double* __restrict__ part, int
 // read_totals split in two: issue() loads this thread's first R partials
 // into registers (before the caller issues its field loads, so that waiting
 // for them does not wait for the fields), total() adds them, and any beyond
-// R NTHR, in the same order as read_totals.
-template <int NV>
+// R NTHR, in the same order as read_totals.  R NTHR should cover the usual
+// partial count (one per row pair: 1024 at 2048^2).
+template <int NV, int R = 4>
 struct Partials {
-  static constexpr int R = 4;
   double v[R][NV];
   template <int NTHR>
   __device__ __forceinline__ void issue(const double* __restrict__ part, int nb) {
@@ -170,6 +170,10 @@ struct Partials {
     block_sum_n<NV, NTHR>(tot, red);
   }
 };
+
+// Partials per thread for a row sweep with PER elements per thread and row:
+// the wave row kernels (PER = 16) run 128 threads, the others 256 or 512.
+__host__ __device__ constexpr int part_regs(int per) { return per >= 16 ? 8 : 4; }
 
 // Last-workgroup reduction, used only by the once-per-solve elementwise
 // kernels (agent-scope stores, fence, ticket).
@@ -222,8 +226,8 @@ struct UpdatePro {
   double sprev, gshift;  // load control: scale of the stored p, mean gap
   T pa[PER], pb[PER], ta[PER], tb[PER], ga[PER], gb[PER];
   bool ma[PER], mb[PER];
-  Partials<NVD> dots;
-  Partials<1> rts;
+  Partials<NVD, part_regs(PER)> dots;
+  Partials<1, part_regs(PER)> rts;
   template <int NTHR>
   __device__ bool issue() {
     if (sc->done) return false;
@@ -356,7 +360,7 @@ struct GapEpi {
   bool ca[PER], cb[PER];
   double acc[NV];
   double s, gref;
-  Partials<3> pu;
+  Partials<3, part_regs(PER)> pu;
   template <int NTHR>
   __device__ bool begin(double*) {
     if (sc->done) return false;
@@ -448,8 +452,8 @@ struct DirPro {
   double ratio, gbar, a_gt;
   T ga[PER], gb[PER], ta[PER], tb[PER];
   bool ca[PER], cb[PER];
-  Partials<3> pu;
-  Partials<NVG> pg;
+  Partials<3, part_regs(PER)> pu;
+  Partials<NVG, part_regs(PER)> pg;
   template <int NTHR>
   __device__ bool issue() {
     if (sc->done) return false;

@@ -3,6 +3,7 @@
 #pragma once
 #include "cg_kernels.h"
 #include "launch.h"
+#include "row_wave.h"
 
 namespace bem {
 
@@ -33,38 +34,36 @@ template <typename T, int MODE>
 hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int it,
                                const hipEvent_t* ev, hipStream_t s) {
   const int nrp = (g.ny + 1) / 2;
-  hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    UpdatePro<T, MODE, PER> up{b.p, b.t, b.g, b.mask, b.sc, b.part, g.nx, nrp, it,
-                               col_energy_blocks<T>(g)};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, UpdatePro<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, up,
-                       b.S, g.nx, g.ny, K.twx);
-    return hipGetLastError();
-  });
+  const int nbc = col_energy_blocks<T>(g);
+  // R2C sweeps: Stockham (their prologues carry most of the work, and the
+  // wave kernels' lower occupancy costs more than their cheaper transform
+  // saves); C2R sweeps: wave kernels at Lx = 2048, except under load
+  // control, whose epilogues do not fit the wave kernel's registers
+  hipError_t e = launch_row_r2c<T, false>(
+      g, K, b.S,
+      [&](auto PERc) {
+        return UpdatePro<T, MODE, decltype(PERc)::value>{b.p,    b.t,    b.g, b.mask, b.sc,
+                                                          b.part, g.nx, nrp, it,     nbc};
+      },
+      s);
   if (e != hipSuccess || (e = mark(ev, 0, s)) != hipSuccess) return e;
   if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
   if ((e = mark(ev, 1, s)) != hipSuccess) return e;
-  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    GapEpi<T, MODE, PER> ge{b.g, b.hd, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, GapEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, b.S,
-                       g.nx, g.ny, K.twx, ge);
-    return hipGetLastError();
-  });
+  e = launch_row_c2r<T, MODE != CG_FORCE>(
+      g, K, b.S,
+      [&](auto PERc) {
+        return GapEpi<T, MODE, decltype(PERc)::value>{b.g,    b.hd, b.p, b.mask, b.sc,
+                                                       b.part, g.nx, nrp, it};
+      },
+      s);
   if (e != hipSuccess || (e = mark(ev, 2, s)) != hipSuccess) return e;
-  e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    DirPro<T, MODE, PER> dp{b.t, b.g, b.p, b.mask, b.sc, b.part, g.nx, nrp, it};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, DirPro<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s, dp,
-                       b.S, g.nx, g.ny, K.twx);
-    return hipGetLastError();
-  });
+  e = launch_row_r2c<T, false>(
+      g, K, b.S,
+      [&](auto PERc) {
+        return DirPro<T, MODE, decltype(PERc)::value>{b.t,    b.g,  b.p, b.mask, b.sc,
+                                                       b.part, g.nx, nrp, it};
+      },
+      s);
   if (e != hipSuccess || (e = mark(ev, 3, s)) != hipSuccess) return e;
   if constexpr (MODE != CG_FORCE) {
     // second convolution: only sum t (C K * t) is needed (Parseval); no
@@ -76,15 +75,12 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
   } else {
     if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
     if ((e = mark(ev, 4, s)) != hipSuccess) return e;
-    e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-      constexpr int L = decltype(LX)::value;
-      constexpr int NT = row_threads(L);
-      constexpr int PER = row_per<L, NT>();
-      DotsEpi<T, MODE, PER> de{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
-      hipLaunchKernelGGL((k_row_c2r<T, L, NT, DotsEpi<T, MODE, PER>>), dim3(nrp), dim3(NT), 0, s,
-                         b.S, g.nx, g.ny, K.twx, de);
-      return hipGetLastError();
-    });
+    e = launch_row_c2r<T, false>(
+        g, K, b.S,
+        [&](auto PERc) {
+          return DotsEpi<T, MODE, decltype(PERc)::value>{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
+        },
+        s);
     if (e != hipSuccess) return e;
     return mark(ev, 5, s);
   }

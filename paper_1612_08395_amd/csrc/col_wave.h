@@ -38,11 +38,12 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   cplx<float>* reg = lds + wv * REG;
 
   // (1) stage the NC columns (rows < LY; zero beyond ny) into the even regions
-  for (int f = threadIdx.x; f < NC * LY; f += NT) {
-    const int cc = f % NC, n = f / NC;
-    cplx<float> x = {0.f, 0.f};
-    if (n < ny) x = S[(size_t)n * lx + c0 + cc];
-    lds[(2 * cc) * REG + n] = x;
+  using Stage = ColStage<float, LY, NC, NT>;
+  {
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j) lds[(2 * Stage::col(j)) * REG + Stage::row(j)] = st.x[j];
   }
   __syncthreads();
   // (2) time layout
@@ -117,11 +118,13 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
     for (int m = 0; m < P; ++m) reg[lane + 64 * m] = cadd(v[m], o[lane + 64 * m]);
   }
   __syncthreads();
-  // (7)
-  for (int f = threadIdx.x; f < NC * ny; f += NT) {
-    const int cc = f % NC, n = f / NC;
-    S[(size_t)n * lx + c0 + cc] = lds[(2 * cc) * REG + n];
-  }
+  // (7) all LDS reads of the thread, then the stores of rows < ny
+  cplx<float> y[Stage::CNT];
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j) y[j] = lds[(2 * Stage::col(j)) * REG + Stage::row(j)];
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j)
+    if (Stage::row(j) < ny) S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
 }
 
 }  // namespace bem
@@ -152,11 +155,12 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
   const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC;
   const int c = c0 + jc;
   cplx<float>* reg = lds + wv * REG;
-  for (int f = threadIdx.x; f < NC * LY; f += NT) {
-    const int cc = f % NC, n = f / NC;
-    cplx<float> x = {0.f, 0.f};
-    if (n < ny) x = S[(size_t)n * lx + c0 + cc];
-    lds[(2 * cc) * REG + n] = x;
+  {
+    using Stage = ColStage<float, LY, NC, NT>;
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j) lds[(2 * Stage::col(j)) * REG + Stage::row(j)] = st.x[j];
   }
   __syncthreads();
   cplx<float> v[P];

@@ -2,6 +2,7 @@
 #include "col_wave.h"
 #include "conv_kernels.h"
 #include "launch.h"
+#include "row_wave.h"
 
 #include <stdlib.h>
 
@@ -23,6 +24,14 @@ int col_width_cap() {
 int col_wave_enabled() {
   static const int on = [] {
     const char* v = getenv("BEM_COL_WAVE");
+    return v ? atoi(v) : 1;
+  }();
+  return on;
+}
+
+int row_wave_enabled() {
+  static const int on = [] {
+    const char* v = getenv("BEM_ROW_WAVE");
     return v ? atoi(v) : 1;
   }();
   return on;
@@ -75,48 +84,24 @@ hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int
 template <typename T>
 hipError_t launch_conv(const Geom& g, const SpecView<T>& K, const T* p, T* u, cplx<T>* S,
                        hipStream_t s) {
-  hipError_t e = dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    PlainLoad<T, PER> pro{p, g.nx};
-    hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT), 0,
-                       s, pro, S, g.nx, g.ny, K.twx);
-    return hipGetLastError();
-  });
+  hipError_t e = launch_row_r2c<T, true>(
+      g, K, S, [&](auto PERc) { return PlainLoad<T, decltype(PERc)::value>{p, g.nx}; }, s);
   if (e != hipSuccess) return e;
   e = launch_col<T>(g, K, S, nullptr, s);
   if (e != hipSuccess) return e;
-  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    PlainStore<T, PER> epi{u, g.nx};
-    hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
-                       0, s, S, g.nx, g.ny, K.twx, epi);
-    return hipGetLastError();
-  });
+  return launch_row_c2r<T, true>(
+      g, K, S, [&](auto PERc) { return PlainStore<T, decltype(PERc)::value>{u, g.nx}; }, s);
 }
 
 template <typename T>
 hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T* p, T* u,
                         cplx<T>* S, hipStream_t s) {
   if (which == 1) return launch_col<T>(g, K, S, nullptr, s);
-  return dispatch_L(g.Lx, [&](auto LX) -> hipError_t {
-    constexpr int L = decltype(LX)::value;
-    constexpr int NT = row_threads(L);
-    constexpr int PER = row_per<L, NT>();
-    if (which == 0) {
-      PlainLoad<T, PER> pro{p, g.nx};
-      hipLaunchKernelGGL((k_row_r2c<T, L, NT, PlainLoad<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
-                         0, s, pro, S, g.nx, g.ny, K.twx);
-    } else {
-      PlainStore<T, PER> epi{u, g.nx};
-      hipLaunchKernelGGL((k_row_c2r<T, L, NT, PlainStore<T, PER>>), dim3((g.ny + 1) / 2), dim3(NT),
-                         0, s, S, g.nx, g.ny, K.twx, epi);
-    }
-    return hipGetLastError();
-  });
+  if (which == 0)
+    return launch_row_r2c<T, true>(
+        g, K, S, [&](auto PERc) { return PlainLoad<T, decltype(PERc)::value>{p, g.nx}; }, s);
+  return launch_row_c2r<T, true>(
+      g, K, S, [&](auto PERc) { return PlainStore<T, decltype(PERc)::value>{u, g.nx}; }, s);
 }
 
 // The wave kernel for FP32 at Ly = 2048 (4 columns per workgroup), else the

@@ -168,6 +168,39 @@ __global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restri
   pro.template finish<NTHR>(red);
 }
 
+// Guarded load of a complex value without control flow (see load_or0).
+template <typename T>
+__device__ __forceinline__ cplx<T> cload_or0(const cplx<T>* __restrict__ a, size_t i, size_t safe,
+                                             bool ok) {
+  const cplx<T> v = a[ok ? i : safe];
+  return {ok ? v.x : T(0), ok ? v.y : T(0)};
+}
+
+// Staging of a group of W adjacent spectrum columns c0.. through LDS.
+// Element f = threadIdx.x + j NTHR of the group is (column f % W, row f / W),
+// rows n < LY.  load() issues every load of the thread before any value is
+// used, with rows >= ny read as zero: the same copy written as a loop with
+// the row guard as a branch waits for each load before issuing the next,
+// which leaves one load per thread in flight.
+template <typename T, int LY, int W, int NTHR>
+struct ColStage {
+  static constexpr int TOT = W * LY;
+  static constexpr int CNT = (TOT + NTHR - 1) / NTHR;
+  cplx<T> x[CNT];
+  __device__ __forceinline__ static bool valid(int j) {
+    return TOT % NTHR == 0 || (int)threadIdx.x + j * NTHR < TOT;
+  }
+  __device__ __forceinline__ static int col(int j) { return ((int)threadIdx.x + j * NTHR) % W; }
+  __device__ __forceinline__ static int row(int j) { return ((int)threadIdx.x + j * NTHR) / W; }
+  __device__ __forceinline__ void load(const cplx<T>* __restrict__ S, int lx, int ny, int c0) {
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) {
+      const bool ok = valid(j) && row(j) < ny;
+      x[j] = cload_or0(S, (size_t)row(j) * lx + c0 + col(j), (size_t)c0, ok);
+    }
+  }
+};
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Remap so that XCD x works on the contiguous block range
 // [x nb/8, (x+1) nb/8): adjacent column groups, which share the 128-byte
@@ -232,24 +265,38 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
   constexpr int STR = lds_len(LY);
   __shared__ cplx<T> lds[2 * W * STR];
   const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
-  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
-    const int c = f % W, n = f / W;
-    cplx<T> x = {T(0), T(0)};
-    if (n < ny) x = S[(size_t)n * lx + c0 + c];
-    lds[(2 * c) * STR + lds_pad(n)] = x;
-    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  using Stage = ColStage<T, LY, W, NTHR>;
+  {
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j)
+      if (Stage::valid(j)) {
+        const int c = Stage::col(j), n = Stage::row(j);
+        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+      }
   }
   __syncthreads();
   fft_lds<T, LY, -1, 2 * W, NTHR, STR>(lds, tw);
   col_multiply<T, LY, W, NTHR, STR>(lds, c0, lx, KT, kpitch);
   __syncthreads();
   fft_lds<T, LY, +1, 2 * W, NTHR, STR>(lds, tw);
-  for (int f = threadIdx.x; f < W * ny; f += NTHR) {
-    const int c = f % W, n = f / W;
-    const cplx<T> e = lds[(2 * c) * STR + lds_pad(n)];
-    const cplx<T> o = lds[(2 * c + 1) * STR + lds_pad(n)];
-    S[(size_t)n * lx + c0 + c] = cadd(e, cmulc(o, tw[n]));
+  // combine the halves for every element first, then store (rows < ny)
+  cplx<T> y[Stage::CNT];
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j) {
+    const int c = Stage::col(j), n = Stage::row(j);
+    if (Stage::valid(j)) {
+      const cplx<T> e = lds[(2 * c) * STR + lds_pad(n)];
+      const cplx<T> o = lds[(2 * c + 1) * STR + lds_pad(n)];
+      y[j] = cadd(e, cmulc(o, tw[n]));
+    }
   }
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j)
+    if (Stage::valid(j) && Stage::row(j) < ny)
+      S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
 }
 
 // Spectral energy of the packed half spectrum.  After the forward column
@@ -285,12 +332,17 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
   __shared__ cplx<T> lds[2 * W * STR];
   __shared__ double red[64];
   const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
-  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
-    const int c = f % W, n = f / W;
-    cplx<T> x = {T(0), T(0)};
-    if (n < ny) x = S[(size_t)n * lx + c0 + c];
-    lds[(2 * c) * STR + lds_pad(n)] = x;
-    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  {
+    using Stage = ColStage<T, LY, W, NTHR>;
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j)
+      if (Stage::valid(j)) {
+        const int c = Stage::col(j), n = Stage::row(j);
+        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+      }
   }
   __syncthreads();
   fft_lds<T, LY, -1, 2 * W, NTHR, STR>(lds, tw);
@@ -392,12 +444,17 @@ __global__ __launch_bounds__(NTHR) void k_col_spectrum(const cplx<double>* __res
   constexpr int STR = lds_len(LY);
   __shared__ cplx<double> lds[2 * W * STR];
   const int c0 = blockIdx.x * W;
-  for (int f = threadIdx.x; f < W * LY; f += NTHR) {
-    const int c = f % W, n = f / W;
-    cplx<double> x = {0.0, 0.0};
-    if (n < ny) x = S[(size_t)n * lx + c0 + c];
-    lds[(2 * c) * STR + lds_pad(n)] = x;
-    lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(x, tw[n]);
+  {
+    using Stage = ColStage<double, LY, W, NTHR>;
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j)
+      if (Stage::valid(j)) {
+        const int c = Stage::col(j), n = Stage::row(j);
+        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+      }
   }
   __syncthreads();
   fft_lds<double, LY, -1, 2 * W, NTHR, STR>(lds, tw);

@@ -19,11 +19,11 @@ int dev_alloc(bem_influence_s* h, void** p, size_t bytes, const char* what) {
 
 template <>
 SpecView<double> spec_view<double>(const bem_influence_s* h) {
-  return {h->KT64, h->twx64, h->twy64, h->twly64};
+  return {h->KT64, h->twx64, h->twy64, h->twly64, h->twlx64};
 }
 template <>
 SpecView<float> spec_view<float>(const bem_influence_s* h) {
-  return {h->KT32, h->twx32, h->twy32, h->twly32};
+  return {h->KT32, h->twx32, h->twy32, h->twly32, h->twlx32};
 }
 
 int influence_build(bem_influence_s* h) {
@@ -41,6 +41,8 @@ int influence_build(bem_influence_s* h) {
   if ((rc = dev_alloc(h, (void**)&h->twy32, My * sizeof(cplx<float>), "twiddles"))) return rc;
   if ((rc = dev_alloc(h, (void**)&h->twly64, g.Ly * sizeof(cplx<double>), "twiddles"))) return rc;
   if ((rc = dev_alloc(h, (void**)&h->twly32, g.Ly * sizeof(cplx<float>), "twiddles"))) return rc;
+  if ((rc = dev_alloc(h, (void**)&h->twlx64, g.Lx * sizeof(cplx<double>), "twiddles"))) return rc;
+  if ((rc = dev_alloc(h, (void**)&h->twlx32, g.Lx * sizeof(cplx<float>), "twiddles"))) return rc;
 
   hipStream_t s = nullptr;
   hipError_t e;
@@ -51,6 +53,8 @@ int influence_build(bem_influence_s* h) {
   if ((e = launch_twiddles(h->twx64, h->twx32, Mx, s)) != hipSuccess) return hip_fail(e, "twiddles");
   if ((e = launch_twiddles(h->twy64, h->twy32, My, s)) != hipSuccess) return hip_fail(e, "twiddles");
   if ((e = launch_wave_twiddles(h->twly64, h->twly32, g.Ly, s)) != hipSuccess)
+    return hip_fail(e, "twiddles");
+  if ((e = launch_wave_twiddles(h->twlx64, h->twlx32, g.Lx, s)) != hipSuccess)
     return hip_fail(e, "twiddles");
   if ((e = launch_influence(h->Kq, h->nx, h->ny, h->dx, h->dy, h->k, s)) != hipSuccess)
     return hip_fail(e, "influence coefficients");
@@ -71,7 +75,7 @@ int influence_build(bem_influence_s* h) {
 
 void influence_release(bem_influence_s* h) {
   void* ptrs[] = {h->Kq, h->KT64, h->KT32, h->twx64, h->twy64, h->twx32, h->twy32,
-                  h->twly64, h->twly32, h->S64, h->S32, h->io64, h->io32, h->epart};
+                  h->twly64, h->twly32, h->twlx64, h->twlx32, h->S64, h->S32, h->io64, h->io32, h->epart};
   for (void* p : ptrs)
     if (p) hipFree(p);
   h->device_bytes = 0;

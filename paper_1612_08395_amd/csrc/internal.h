@@ -23,6 +23,8 @@ struct bem_influence_s {
   bem::cplx<float>* twy32 = nullptr;
   bem::cplx<double>* twly64 = nullptr;  // wave-FFT table for length Ly (Ly = 64 P)
   bem::cplx<float>* twly32 = nullptr;
+  bem::cplx<double>* twlx64 = nullptr;  // the same for length Lx (row sweeps)
+  bem::cplx<float>* twlx32 = nullptr;
   // lazily allocated scratch of the convolution entry points
   bem::cplx<double>* S64 = nullptr;
   bem::cplx<float>* S32 = nullptr;

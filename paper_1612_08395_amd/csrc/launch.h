@@ -22,6 +22,7 @@ struct SpecView {
   const cplx<T>* twx;      // Mx-point twiddles
   const cplx<T>* twy;      // My-point twiddles
   const cplx<T>* twly;     // wave-FFT inter-step table [k1][lane] for length Ly (or null)
+  const cplx<T>* twlx;     // the same table for length Lx (row sweeps)
 };
 
 // Workgroup sizes and column-group widths, shared by launchers and the
@@ -43,6 +44,11 @@ __host__ __device__ constexpr int col_width_lds(int LY) {
 
 // Tuning knob: BEM_COL_WIDTH (1, 2, 4, 8, 16) caps the column-group width.
 int col_width_cap();
+
+// Tuning knob BEM_ROW_WAVE: 1 (default) = wave-FFT row sweeps for FP32 at
+// Lx = 2048, 0 = LDS Stockham row sweeps everywhere.
+int row_wave_enabled();
+inline bool row_wave(const Geom& g) { return g.Lx == 2048 && row_wave_enabled(); }
 
 template <typename T>
 inline int col_width(int LY, int lx) {

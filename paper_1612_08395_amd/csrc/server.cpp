@@ -250,7 +250,7 @@ int bem_footprint(int nx, int ny, int precision, long long* influence_bytes,
   const long long kpitch = ((Ly + 1) + 63) / 64 * 64;
   const long long n = (long long)nx * ny;
   if (influence_bytes)
-    *influence_bytes = n * 8 + (Lx + 1) * kpitch * 12 + (long long)(Mx + My + Ly) * 24;
+    *influence_bytes = n * 8 + (Lx + 1) * kpitch * 12 + (long long)(Mx + My + Ly + Lx) * 24;
   const long long ts = precision == BEM_FP64 ? 8 : 4;
   if (state_bytes)
     *state_bytes = n * (1 + 8 + 8) + state_partial_bytes() + 512 + 4 * n * ts +
