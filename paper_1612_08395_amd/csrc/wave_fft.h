@@ -105,13 +105,19 @@ __device__ __forceinline__ void twiddle_lk1(cplx<T> (&v)[P], const cplx<T>* __re
   }
 }
 
+// Value of the partner lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2].
+// Every lane has a source, so the move needs no initialised old value (with
+// update_dpp(0, ...) the compiler materialises the zero in an extra move).
+__device__ __forceinline__ int lane_xor1_bits(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+}
 __device__ __forceinline__ float lane_xor1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  return __int_as_float(lane_xor1_bits(__float_as_int(v)));
 }
 __device__ __forceinline__ double lane_xor1(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  const int lo = lane_xor1_bits((int)(b & 0xffffffff));
+  const int hi = lane_xor1_bits((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

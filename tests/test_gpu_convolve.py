@@ -36,7 +36,7 @@ def test_fp64_matches_direct_sum(ny, nx, k):
 
 @pytest.mark.parametrize("ny,nx,k", [(128, 128, 0.5), (100, 37, -0.3), (301, 512, 0.0),
                                      (1024, 1024, -0.8), (63, 2048, 0.3), (1500, 700, 0.2),
-                                     (2100, 130, -0.4), (2048, 2048, 0.3)])
+                                     (2100, 130, -0.4), (2048, 2048, 0.3), (37, 1500, 0.6)])
 def test_fp64_and_fp32_match_oracle_fft(ny, nx, k):
     from paper_1612_08395_amd import bem
     torch = _torch()

@@ -85,6 +85,30 @@ def test_ragged_and_degenerate_grids(ny, nx, k, shape):
     K.free()
 
 
+@pytest.mark.parametrize("ny,nx,k", [(41, 1300, 0.3), (32, 2048, 0.2)])
+def test_wide_grids_mixed(ny, nx, k):
+    # 1024 < nx <= 2048: the row spectrum has 2048 columns, so the mixed loop
+    # runs its C2R sweeps on the wave-FFT kernels (ragged nx, odd ny: a row
+    # pair with one row)
+    bem = _bem()
+    announce("wide-mixed", ny, nx, k)
+    nu, L = 0.3, 1.0
+    dx = L / nx
+    Kq = inf.influence_quarter(nx, ny, dx, dx, k)
+    C = m.compliance(k, nu)
+    xs = (np.arange(nx) + 0.5) * dx - 0.5 * L
+    ys = (np.arange(ny) + 0.5) * dx - 0.5 * ny * dx
+    h = (xs[None, :] ** 2 + 4.0 * ys[:, None] ** 2) / 2.0
+    d = float(np.quantile(h, 0.2))
+    ref = so.solve_nonadhesive(Kq, C, h, d, tol=1e-12, conv=FFTConvolver(Kq, C, workers=-1))
+    K = bem.bem_influence(nx, ny, dx, k, nu)
+    _, rm, pm, cm, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, precision=bem.BEM_MIXED))
+    assert rm.status in (0, bem.BEM_EFLOOR)
+    assert rel_l2(pm, ref.p) <= MIXED_TOL
+    assert _count_close(rm.n_contact, ref.contact.sum())
+    K.free()
+
+
 def test_no_contact_and_full_contact():
     bem = _bem()
     announce("degenerate-contact")
