@@ -9,8 +9,11 @@ transform): k = 0.3, nu = 0.3, side L = 1, Gaussian heights with
 C(q) ~ q^-2(1+H), H = 0.7, roll-off q0 = 8 (2 pi / L), cut-off
 q1 = 512 (2 pi / L), rms height 1e-3 L, seed 1612.  One bench step is an
 indentation sweep of 20 depths d_s = s d10 / 20 (d10: depth of 10 % contact
-area), each a full CG solve warm-started from the previous depth, with the
-gap profile resident in HBM.  value = solves per second of the mixed path.
+area), each a full CG solve, with the gap profile resident in HBM, run by
+bem_sweep_dev as --chains (default 2) concurrent warm-start chains (chain c
+solves depths c, c + chains, ..., each warm-started from the chain's previous
+depth).  value = solves per second of the mixed path; the same sweep as one
+chain is reported beside it.
 
 Prints one JSON line.  Also reports the FP64 path, the mixed-vs-FP64
 pressure error per depth, the roofline of the dominant kernel and the FP64
@@ -86,26 +89,38 @@ def run_sweep(bem, K, h_dev, depths, precision, keep_p=False, torch=None):
     return out, p_list
 
 
-def timed(bem, K, h_dev, depths, precision, steps, warmup, torch):
-    """Times `steps` sweeps, uninstrumented.  Then one more sweep of the same
-    depths runs with the library's solver clock (HIP events on the solver
-    stream around every CG launch; the events cost about 10 % of a sweep, so
-    they stay out of the timed steps) for the per-kernel durations."""
+def sweep_dev(bem, K, h_dev, depths, precision, chains):
+    """One sweep through bem_sweep_dev (h resident on the device) from a
+    fresh state, its steps split over `chains` concurrent warm-start chains."""
+    st = bem.bem_state_create(K)
+    _, res = bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(precision=precision), depths,
+                               chains=chains, state=st)
+    st.free()
+    return [r.as_dict() for r in res]
+
+
+def timed(bem, K, h_dev, depths, precision, steps, warmup, torch, chains, clock=True):
+    """Times `steps` sweeps, uninstrumented.  Then (clock=True) one more sweep
+    of the same depths runs as a single chain with the library's solver clock
+    (HIP events on the solver stream around every CG launch; the events cost
+    about 10 % of a sweep, so they stay out of the timed steps) for the
+    per-kernel durations."""
     for _ in range(warmup):
-        run_sweep(bem, K, h_dev, depths, precision)
+        sweep_dev(bem, K, h_dev, depths, precision, chains)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for _ in range(steps):
-        r, _ = run_sweep(bem, K, h_dev, depths, precision)
-        results.append(r)
+        results.append(sweep_dev(bem, K, h_dev, depths, precision, chains))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    bem.bem_clock_start()
-    run_sweep(bem, K, h_dev, depths, precision)
-    torch.cuda.synchronize()
-    clock = bem.bem_clock_stop()
-    return (t1 - t0), results, clock
+    clk = None
+    if clock:
+        bem.bem_clock_start()
+        sweep_dev(bem, K, h_dev, depths, precision, 1)
+        torch.cuda.synchronize()
+        clk = bem.bem_clock_stop()
+    return (t1 - t0), results, clk
 
 
 def roofline(bem, K, clock, torch):
@@ -372,6 +387,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests per serving run (0: skip the serving measurement)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--chains", type=int, default=2,
+                    help="concurrent warm-start chains of the timed sweeps (1..8)")
     ap.add_argument("--find-d10-4096", action="store_true")
     ap.add_argument("--no-big-grid", action="store_true",
                     help="skip the 4096^2 (HBM-resident) mixed sweep")
@@ -379,8 +396,8 @@ def main():
                     help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
                          "and a 1 GiB device copy, for hardware-counter runs")
     args = ap.parse_args()
-    if args.steps < 1 or args.fp64_steps < 1 or args.warmup < 0:
-        ap.error("--steps and --fp64-steps must be >= 1, --warmup >= 0")
+    if args.steps < 1 or args.fp64_steps < 1 or args.warmup < 0 or not 1 <= args.chains <= 8:
+        ap.error("--steps and --fp64-steps must be >= 1, --warmup >= 0, 1 <= --chains <= 8")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -417,9 +434,13 @@ def main():
 
     log("[bench] timed mixed sweeps")
     t32, res32, clk32 = timed(bem, K, h_dev, depths, bem.BEM_MIXED, args.steps, args.warmup,
-                              torch)
+                              torch, args.chains)
+    t32s, res32s, _ = timed(bem, K, h_dev, depths, bem.BEM_MIXED, args.steps, 0, torch, 1,
+                            clock=False)
     log("[bench] timed FP64 sweeps")
-    t64, res64, clk64 = timed(bem, K, h_dev, depths, bem.BEM_FP64, args.fp64_steps, 0, torch)
+    # FP64: one chain (its kernels overlap less, and a second chain measured
+    # slower than the sequential sweep)
+    t64, res64, clk64 = timed(bem, K, h_dev, depths, bem.BEM_FP64, args.fp64_steps, 0, torch, 1)
     it32 = [x["iters"] for x in res32[-1]]
     it64 = [x["iters"] for x in res64[-1]]
     solves32 = N_DEPTHS * args.steps / t32
@@ -441,9 +462,15 @@ def main():
                                "k=0.3 nu=0.3, 20 depths to 10% contact, mixed precision",
                    "n": N, "padded": 2 * N, "k": K_EXP, "nu": NU, "H": H_EXP,
                    "q0_over_2pi_L": Q0, "q1_over_2pi_L": Q1, "rms_over_L": RMS, "seed": SEED,
-                   "depths_per_step": N_DEPTHS, "d10": d10},
+                   "depths_per_step": N_DEPTHS, "d10": d10, "chains": args.chains,
+                   "sweep": f"bem_sweep_dev: {args.chains} concurrent warm-start chains "
+                            f"(chain c solves depths c, c + {args.chains}, ...)"},
+        "single_chain": {"value": round(N_DEPTHS * args.steps / t32s, 3), "unit": "solves/s",
+                         "iters_per_solve": round(sum(x["iters"] for x in res32s[-1])
+                                                  / N_DEPTHS, 2)},
         "roofline": roof,
         "fp64": {"value": round(solves64, 3), "unit": "solves/s", "steps": args.fp64_steps,
+                 "chains": 1,
                  "ms_per_step": round(t64 / args.fp64_steps * 1e3, 3),
                  "iters_per_solve": round(sum(it64) / len(it64), 2),
                  "loop_GBps_algorithmic": round(loop64, 1),

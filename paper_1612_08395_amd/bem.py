@@ -201,6 +201,8 @@ _f_solve_dev = _sig("bem_solve_dev", _c_int, [_vp, _vp, ctypes.POINTER(Params), 
                                               _vp, ctypes.POINTER(Result), _vp])
 _f_sweep = _sig("bem_sweep", _c_int, [_vp, _dp, ctypes.POINTER(Params), _dp, _c_int, _vp,
                                       ctypes.POINTER(Result), _vp])
+_f_sweep_dev = _sig("bem_sweep_dev", _c_int, [_vp, _vp, ctypes.POINTER(Params), _dp, _c_int,
+                                              _c_int, _vp, ctypes.POINTER(Result), _vp])
 _f_c1 = _sig("bem_c1", _c_double, [_c_double])
 _f_p_crit = _sig("bem_p_crit", _c_double, [_c_double, _c_double, _c_double, _c_double,
                                            _c_double, _c_double])
@@ -306,6 +308,17 @@ def bem_sweep(K, h, prm, d_list, state=None, stream=None):
     res = (Result * len(d))()
     rc = _f_sweep(K.handle, h.ctypes.data_as(_dp), ctypes.byref(prm), d.ctypes.data_as(_dp),
                   len(d), state.handle if state is not None else None, res, _stream(stream))
+    _check(rc)
+    return rc, list(res)
+
+
+def bem_sweep_dev(K, h, prm, d_list, chains=1, state=None, stream=None):
+    """h: device array (float64, ny x nx).  Returns (status, [Result, ...])."""
+    d = np.ascontiguousarray(d_list, dtype=np.float64)
+    res = (Result * len(d))()
+    rc = _f_sweep_dev(K.handle, _ptr(h), ctypes.byref(prm), d.ctypes.data_as(_dp), len(d),
+                      int(chains), state.handle if state is not None else None, res,
+                      _stream(stream))
     _check(rc)
     return rc, list(res)
 

@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -443,6 +445,50 @@ int solve_common(bem_influence_t K, const double* h_dev, const bem_params* prm, 
   return rc;
 }
 
+// The steps i = first, first + stride, ... of a sweep, warm-started from one
+// to the next in `state` on stream s.  With stride 1 this is the sweep of
+// Section 3.1: with adhesion, a step whose value is below the previous
+// step's is a pull-off step, every other step a loading (non-adhesive) solve.
+int sweep_steps(bem_influence_t K, const double* h_dev, const bem_params* prm,
+                const double* d_list, int n_steps, int first, int stride, bem_state_t state,
+                bem_result* res, hipStream_t s) {
+  int worst = BEM_OK;
+  const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
+  for (int i = first; i < n_steps; i += stride) {
+    bem_params P = *prm;
+    if (prm->control == BEM_CTRL_FORCE)
+      P.F = d_list[i];
+    else
+      P.d = d_list[i];
+    const bool unloading = adhesive && i > 0 && d_list[i] < d_list[i - 1];
+    if (adhesive && !unloading) {
+      P.gamma = 0.0;
+      P.p_crit = 0.0;
+    }
+    const int r = solve_common(K, h_dev, &P, state, nullptr, nullptr, nullptr, true, &res[i], s);
+    if (r < 0) return r;
+    worst = worse(worst, r);
+  }
+  return worst;
+}
+
+// Carry src's warm-start data (pressure, contact set) into dst, a state of
+// the same handle, on stream s.
+int state_copy(bem_state_s* dst, const bem_state_s* src, hipStream_t s) {
+  if (src->precision < 0 || !src->has_p) return BEM_OK;
+  int rc = ensure_precision(dst, src->precision, s);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(dst->p, src->p, src->n * tsize(src->precision),
+                                hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst->mask, src->mask, src->n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "state copy");
+  dst->has_p = src->has_p;
+  dst->has_mask = src->has_mask;
+  dst->pending_import = dst->import_mask = false;
+  std::copy(src->last_iters, src->last_iters + 3, dst->last_iters);
+  return BEM_OK;
+}
+
 int upload_h(bem_state_t st, const double* h, hipStream_t s) {
   for (size_t i = 0; i < st->n; ++i)
     if (!is_finite(h[i])) return set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
@@ -600,28 +646,96 @@ int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const d
     state = tmp;
   }
   rc = upload_h(state, h, s);
-  int worst = BEM_OK;
-  const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
-  for (int i = 0; rc == BEM_OK && i < n_steps; ++i) {
-    bem_params P = *prm;
-    if (prm->control == BEM_CTRL_FORCE)
-      P.F = d_list[i];
-    else
-      P.d = d_list[i];
-    const bool unloading = adhesive && i > 0 && d_list[i] < d_list[i - 1];
-    if (adhesive && !unloading) {
-      P.gamma = 0.0;
-      P.p_crit = 0.0;
-    }
-    int r = solve_common(K, state->h64, &P, state, nullptr, nullptr, nullptr, true, &res[i], s);
-    if (r < 0) {
-      rc = r;
-      break;
-    }
-    worst = worse(worst, r);
-  }
+  if (rc == BEM_OK) rc = sweep_steps(K, state->h64, prm, d_list, n_steps, 0, 1, state, res, s);
   if (tmp) bem_state_free(tmp);
-  return rc < 0 ? rc : worst;
+  return rc;
+}
+
+int bem_sweep_dev(bem_influence_t K, const double* h, const bem_params* prm, const double* d_list,
+                  int n_steps, int chains, bem_state_t state, bem_result* res, void* stream) {
+  clear_error();
+  if (!K || !h || !prm || !d_list || !res || n_steps < 0 || chains < 1 || chains > 8)
+    return set_error(BEM_EINVAL, "bem_sweep_dev: invalid argument (1 <= chains <= 8)");
+  for (int i = 0; i < n_steps; ++i)
+    if (!is_finite(d_list[i])) return set_error(BEM_EINVAL, "bem_sweep_dev: non-finite step value");
+  if (state && state->K != K)
+    return set_error(BEM_EINVAL, "bem_sweep_dev: state belongs to another influence handle");
+  const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
+  if (adhesive && chains > 1)
+    return set_error(BEM_EUNSUPPORTED,
+                     "bem_sweep_dev: an adhesive sweep depends on its path; chains must be 1");
+  hipStream_t s0 = (hipStream_t)stream;
+  chains = std::max(1, std::min(chains, n_steps));
+  bem_state_t tmp = nullptr;
+  int rc;
+  if (!state) {
+    if ((rc = bem_state_create(K, &tmp))) return rc;
+    state = tmp;
+  }
+  if (chains == 1) {
+    rc = sweep_steps(K, h, prm, d_list, n_steps, 0, 1, state, res, s0);
+    if (tmp) bem_state_free(tmp);
+    return rc;
+  }
+  // chain c > 0: a state and a non-blocking stream of its own, ordered
+  // after the work already queued on the caller's stream
+  std::vector<bem_state_t> st(chains, nullptr);
+  std::vector<hipStream_t> ss(chains, nullptr);
+  st[0] = state;
+  ss[0] = s0;
+  hipEvent_t ready = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ready, s0);
+  rc = e == hipSuccess ? BEM_OK : hip_fail(e, "bem_sweep_dev: event");
+  for (int c = 1; rc == BEM_OK && c < chains; ++c) {
+    rc = bem_state_create(K, &st[c]);
+    if (rc == BEM_OK) {
+      e = hipStreamCreateWithFlags(&ss[c], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ss[c], ready, 0);
+      if (e != hipSuccess) rc = hip_fail(e, "bem_sweep_dev: stream");
+    }
+  }
+  if (rc == BEM_OK) {
+    std::vector<int> rcs(chains, BEM_OK);
+    std::vector<std::string> msgs(chains);
+    auto run = [&](int c) {
+      if (c > 0) (void)hipSetDevice(K->device);
+      rcs[c] = sweep_steps(K, h, prm, d_list, n_steps, c, chains, st[c], res, ss[c]);
+      if (rcs[c] < 0) msgs[c] = bem_last_error();
+      const hipError_t es = hipStreamSynchronize(ss[c]);
+      if (es != hipSuccess && rcs[c] >= 0) {
+        rcs[c] = BEM_EDEVICE;
+        msgs[c] = std::string("bem_sweep_dev: ") + hipGetErrorString(es);
+      }
+    };
+    std::vector<std::thread> workers;
+    for (int c = 1; c < chains; ++c) workers.emplace_back(run, c);
+    run(0);
+    for (auto& w : workers) w.join();
+    int worst = BEM_OK;
+    const char* msg = nullptr;
+    for (int c = 0; c < chains; ++c) {
+      if (rcs[c] < 0 && !msg) msg = msgs[c].c_str();
+      worst = worse(worst, rcs[c]);
+    }
+    if (msg) set_error(worst, "%s", msg);
+    rc = worst;
+    // the caller's state ends with the last step's pressure and contact set
+    const int last = (n_steps - 1) % chains;
+    if (rc >= 0 && last != 0) {
+      const int r = state_copy(state, st[last], s0);
+      rc = r ? r : rc;
+      if (r == BEM_OK && (e = hipStreamSynchronize(s0)) != hipSuccess)
+        rc = hip_fail(e, "bem_sweep_dev: state copy");
+    }
+  }
+  for (int c = 1; c < chains; ++c) {
+    if (ss[c]) (void)hipStreamDestroy(ss[c]);
+    if (st[c]) bem_state_free(st[c]);
+  }
+  if (ready) (void)hipEventDestroy(ready);
+  if (tmp) bem_state_free(tmp);
+  return rc;
 }
 
 double bem_c1(double k) { return c1_table(k); }

@@ -160,6 +160,59 @@ def test_warm_start_state_roundtrip_and_sweep():
     K.free()
 
 
+@pytest.mark.parametrize("chains", [1, 2, 3])
+def test_sweep_dev_concurrent_chains(chains):
+    # bem_sweep_dev: h read on the device, steps split over concurrent
+    # warm-start chains; every step against the oracle, and the caller's
+    # state left with the last step's solution
+    import torch
+    bem = _bem()
+    announce("sweep-dev", chains)
+    n, L, k, nu = 96, 1.0, 0.4, 0.3
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    h = inputs.fractal_gap(n, L, 0.8, 4 * 2 * math.pi / L, 32 * 2 * math.pi / L, 1e-3 * L, 77)
+    ds = [float(np.quantile(h, q)) for q in (0.02, 0.04, 0.06, 0.08, 0.10, 0.12, 0.14)]
+    refs = [so.solve_nonadhesive(Kq, C, h, d, tol=1e-12, conv=conv) for d in ds]
+    K = bem.bem_influence(n, n, dx, k, nu)
+    h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
+    st = bem.bem_state_create(K)
+    rc, sw = bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(), ds, chains=chains, state=st)
+    assert rc == 0
+    for r, ref in zip(sw, refs):
+        assert r.status == 0
+        assert r.F == pytest.approx(so.force(ref.p, dx, dx), rel=1e-10)
+        assert r.n_contact == int(ref.contact.sum())
+    p_s, c_s = bem.bem_state_get(st)
+    assert rel_l2(p_s, refs[-1].p) <= FP64_TOL
+    assert np.array_equal(c_s.astype(bool), refs[-1].contact)
+    # mixed precision through the same chains
+    rc, swm = bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(precision=bem.BEM_MIXED), ds,
+                                chains=chains)
+    for r, ref in zip(swm, refs):
+        assert r.status in (0, bem.BEM_EFLOOR)
+        assert r.F == pytest.approx(so.force(ref.p, dx, dx), rel=2e-5)
+        assert _count_close(r.n_contact, ref.contact.sum())
+    st.free()
+    K.free()
+
+
+def test_sweep_dev_argument_errors():
+    import torch
+    bem = _bem()
+    announce("sweep-dev-errors")
+    n = 32
+    K = bem.bem_influence(n, n, 1.0 / n, 0.0, 0.3)
+    h_dev = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    for chains in (0, 9):
+        with pytest.raises(bem.BemError):
+            bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(), [0.01], chains=chains)
+    with pytest.raises(bem.BemError):   # adhesive sweeps depend on their path
+        bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(gamma=1e-3), [0.01, 0.0], chains=2)
+    with pytest.raises(bem.BemError):
+        bem.bem_sweep_dev(K, h_dev, bem.bem_params_init(), [0.01, float("nan")], chains=2)
+    K.free()
+
+
 def test_adhesive_step_transitions_parity():
     # Section 3.1: non-adhesive preload, then pull-off steps with the
     # detachment criterion; each step compared with the oracle's own step.
