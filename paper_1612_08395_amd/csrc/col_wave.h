@@ -56,38 +56,86 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
 #pragma unroll
     for (int m = 0; m < P; ++m) v[m] = cmul(v[m], tw[lane + 64 * m]);
   }
-  // (3)
-  wave_fft_fwd<float, P>(v, reg, twl, lane);
+  // (3) forward transform up to its lane-pair step
+  wave_fft_fwd_core<float, P>(v, reg, twl, lane);
   // (4) spectrum multiply; K(ky) is even: K(ky) = K(2 LY - ky)
-  if (c != 0) {
-    const float* Kc = KT + (size_t)c * kpitch;
-    if constexpr (P == 32) {
-      // lane (k1, h), register r: f = k1 + 32 r + 1024 h, so the folded
-      // index is kq0 + 64 r (h = 0) or kq0 - 64 r (h = 1)
+  if constexpr (P == 32) {
+    if (c != 0) {
+      // The forward lane-pair step, the multiply and the inverse lane-pair
+      // step in one exchange.  Lane (k1, h), register r holds E (h = 0) or O
+      // (h = 1) of frequencies f_lo = k1 + 32 r and f_hi = f_lo + 1024; with
+      // w = w_64^r and K_lo, K_hi the kernel spectrum there,
+      //   X_lo = E + w O, X_hi = E - w O,  Y = K X,
+      //   h = 0 keeps Y_lo + Y_hi        = A E + D (w O),
+      //   h = 1 keeps (Y_lo - Y_hi) w^-1 = A O + D (conj(w) E),
+      // A = K_lo + K_hi, D = K_lo - K_hi: each lane needs its partner's
+      // value and kernel weight only.  The folded spectrum index runs as
+      // kq0 + 64 r (h = 0) or kq0 - 64 r (h = 1).
+      const float* Kc = KT + (size_t)c * kpitch;
       const int k1 = lane >> 1, h = lane & 1;
+      const float sg = h ? -1.f : 1.f;
       int kq = h ? LY - 2 * k1 - parity : 2 * k1 + parity;
       const int dk = h ? -64 : 64;
+      // all weights in flight at once (loaded inside the loop below, each
+      // would be waited for before the next is issued)
+      float kw[P];
 #pragma unroll
       for (int r = 0; r < P; ++r) {
-        v[r] = cscale(v[r], Kc[kq]);
+        kw[r] = Kc[kq];
         kq += dk;
       }
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const float ko = kw[r];
+        const float kp = lane_xor1(ko);
+        const float A = ko + kp, D = sg * (ko - kp);
+        const cplx<float> b = {lane_xor1(v[r].x), lane_xor1(v[r].y)};
+        // b w (h = 0) or b conj(w) (h = 1), w = exp(-2 pi i r / 64)
+        cplx<float> tb = b;
+        const int t = 2 * r;
+        if (t == 32) {
+          tb = {sg * b.y, -sg * b.x};
+        } else if (t != 0) {
+          const float cs = (float)cos128(t), sn = sg * (float)(-sin128(t));
+          tb = {b.x * cs - b.y * sn, b.x * sn + b.y * cs};
+        }
+        v[r] = {A * v[r].x + D * tb.x, A * v[r].y + D * tb.y};
+      }
     } else {
+      // packed column 0: Z'[k] = ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]);
+      // bins k and -k of one parity half sit in different lanes, so swap
+      // via the wave's LDS region
+      wave_fwd_pair<float>(v, lane);
+      const float* K0 = KT;
+      const float* K1 = KT + (size_t)lx * kpitch;
+#pragma unroll
+      for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int f = wave_freq<P>(lane, r);
+        const int fp = parity ? (LY - 1 - f) : ((LY - f) & (LY - 1));
+        const cplx<float> z1 = reg[fp];
+        const int ky = 2 * f + parity;
+        const int kq = ky <= LY ? ky : 2 * LY - ky;
+        const float a = 0.5f * (K0[kq] + K1[kq]), b = 0.5f * (K0[kq] - K1[kq]);
+        v[r] = {a * v[r].x + b * z1.x, a * v[r].y - b * z1.y};
+      }
+      wave_lds_sync();
+      wave_inv_pair<float>(v, lane);
+    }
+  } else {
+    if (c != 0) {
+      const float* Kc = KT + (size_t)c * kpitch;
 #pragma unroll
       for (int r = 0; r < P; ++r) {
         const int ky = 2 * wave_freq<P>(lane, r) + parity;
         const int kq = ky <= LY ? ky : 2 * LY - ky;
         v[r] = cscale(v[r], Kc[kq]);
       }
-    }
-  }
-  // packed column 0: Z'[k] = ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]); bins
-  // k and -k of one parity half sit in different lanes, so swap via the
-  // wave's LDS region
-  if (c == 0) {
-    const float* K0 = KT;
-    const float* K1 = KT + (size_t)lx * kpitch;
-    {
+    } else {
+      const float* K0 = KT;
+      const float* K1 = KT + (size_t)lx * kpitch;
 #pragma unroll
       for (int r = 0; r < P; ++r) reg[wave_freq<P>(lane, r)] = v[r];
       wave_lds_sync();
@@ -104,8 +152,8 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
       wave_lds_sync();
     }
   }
-  // (5)
-  wave_fft_inv<float, P>(v, reg, twl, lane);
+  // (5) inverse transform after its lane-pair step
+  wave_fft_inv_core<float, P>(v, reg, twl, lane);
   // (6) combine the two halves: y[n] = e[n] + conj(w^n) o[n]
   if (parity) {
 #pragma unroll
@@ -180,11 +228,14 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
       const int k1 = lane >> 1, h = lane & 1;
       int kq = h ? LY - 2 * k1 - parity : 2 * k1 + parity;
       const int dk = h ? -64 : 64;
+      float kw[P];   // all weights in flight at once
 #pragma unroll
       for (int r = 0; r < P; ++r) {
-        e += energy_term(v[r], Kc[kq]);
+        kw[r] = Kc[kq];
         kq += dk;
       }
+#pragma unroll
+      for (int r = 0; r < P; ++r) e += energy_term(v[r], kw[r]);
     } else {
 #pragma unroll
       for (int r = 0; r < P; ++r) {

@@ -142,10 +142,12 @@ __device__ __forceinline__ int wave_freq(int lane, int r) {
   else return lane + 64 * r;
 }
 
-// Forward transform.  `reg` is this wave's private LDS region (P * 65).
+// Forward transform up to (not including) the lane-pair step of P = 32:
+// register DFT, twiddle, transpose, register DFT.  `reg` is this wave's
+// private LDS region (P * 65).
 template <typename T, int P>
-__device__ __forceinline__ void wave_fft_fwd(cplx<T> (&v)[P], cplx<T>* reg,
-                                             const cplx<T>* __restrict__ twl, int lane) {
+__device__ __forceinline__ void wave_fft_fwd_core(cplx<T> (&v)[P], cplx<T>* reg,
+                                                  const cplx<T>* __restrict__ twl, int lane) {
   static_assert(P == 32 || P == 64, "wave FFT sizes");
   reg_dft<T, P, -1>(v);
   twiddle_lk1<T, P, -1>(v, twl, lane);
@@ -162,39 +164,53 @@ __device__ __forceinline__ void wave_fft_fwd(cplx<T> (&v)[P], cplx<T>* reg,
   }
   wave_lds_sync();
   reg_dft<T, P, -1>(v);
-  if constexpr (P == 32) {
-    // lane pair (h = 0: E, h = 1: O): X_lo = E + w O, X_hi = E - w O.  The O
-    // lane multiplies by w before the exchange; each lane then adds (E) or
-    // subtracts (O) its own value from what it receives.
-    const bool hi = lane & 1;
-    const T sg = hi ? T(-1) : T(1);
+}
+
+// Lane-pair step of the forward transform, P = 32 (h = 0: E, h = 1: O):
+// X_lo = E + w O, X_hi = E - w O with w = w_64^k2.  The O lane multiplies
+// by w before the exchange; each lane then adds (E) or subtracts (O) its own
+// value from what it receives.
+template <typename T>
+__device__ __forceinline__ void wave_fwd_pair(cplx<T> (&v)[32], int lane) {
+  const bool hi = lane & 1;
+  const T sg = hi ? T(-1) : T(1);
 #pragma unroll
-    for (int k2 = 0; k2 < 32; ++k2) {
-      const cplx<T> wv = mul_wn<T, -1>(v[k2], k2, 64);
-      const cplx<T> x = hi ? wv : v[k2];
-      const cplx<T> o = {lane_xor1(x.x), lane_xor1(x.y)};
-      v[k2] = {o.x + sg * x.x, o.y + sg * x.y};
-    }
+  for (int k2 = 0; k2 < 32; ++k2) {
+    const cplx<T> wv = mul_wn<T, -1>(v[k2], k2, 64);
+    const cplx<T> x = hi ? wv : v[k2];
+    const cplx<T> o = {lane_xor1(x.x), lane_xor1(x.y)};
+    v[k2] = {o.x + sg * x.x, o.y + sg * x.y};
   }
 }
 
-// Inverse (unnormalised) transform from the permuted frequency layout back
-// to y[lane + 64 m] in v[m].
+// Forward transform.
 template <typename T, int P>
-__device__ __forceinline__ void wave_fft_inv(cplx<T> (&v)[P], cplx<T>* reg,
+__device__ __forceinline__ void wave_fft_fwd(cplx<T> (&v)[P], cplx<T>* reg,
                                              const cplx<T>* __restrict__ twl, int lane) {
-  if constexpr (P == 32) {
-    // h = 0 keeps X_lo + X_hi, h = 1 keeps (X_lo - X_hi) w^(-k2)
-    const bool hi = lane & 1;
-    const T sg = hi ? T(-1) : T(1);
+  wave_fft_fwd_core<T, P>(v, reg, twl, lane);
+  if constexpr (P == 32) wave_fwd_pair<T>(v, lane);
+}
+
+// Lane-pair step of the inverse transform, P = 32: h = 0 keeps
+// X_lo + X_hi, h = 1 keeps (X_lo - X_hi) w^(-k2).
+template <typename T>
+__device__ __forceinline__ void wave_inv_pair(cplx<T> (&v)[32], int lane) {
+  const bool hi = lane & 1;
+  const T sg = hi ? T(-1) : T(1);
 #pragma unroll
-    for (int k2 = 0; k2 < 32; ++k2) {
-      const cplx<T> o = {lane_xor1(v[k2].x), lane_xor1(v[k2].y)};
-      const cplx<T> sum = {o.x + sg * v[k2].x, o.y + sg * v[k2].y};
-      const cplx<T> tw = mul_wn<T, +1>(sum, k2, 64);
-      v[k2] = hi ? tw : sum;
-    }
+  for (int k2 = 0; k2 < 32; ++k2) {
+    const cplx<T> o = {lane_xor1(v[k2].x), lane_xor1(v[k2].y)};
+    const cplx<T> sum = {o.x + sg * v[k2].x, o.y + sg * v[k2].y};
+    const cplx<T> tw = mul_wn<T, +1>(sum, k2, 64);
+    v[k2] = hi ? tw : sum;
   }
+}
+
+// Inverse transform after the lane-pair step: register DFT, transpose,
+// conjugate twiddle, register DFT; returns y[lane + 64 m] in v[m].
+template <typename T, int P>
+__device__ __forceinline__ void wave_fft_inv_core(cplx<T> (&v)[P], cplx<T>* reg,
+                                                  const cplx<T>* __restrict__ twl, int lane) {
   reg_dft<T, P, +1>(v);
   if constexpr (P == 32) {
     const int k1 = lane >> 1, h = lane & 1;
@@ -210,6 +226,15 @@ __device__ __forceinline__ void wave_fft_inv(cplx<T> (&v)[P], cplx<T>* reg,
   wave_lds_sync();
   twiddle_lk1<T, P, +1>(v, twl, lane);
   reg_dft<T, P, +1>(v);
+}
+
+// Inverse (unnormalised) transform from the permuted frequency layout back
+// to y[lane + 64 m] in v[m].
+template <typename T, int P>
+__device__ __forceinline__ void wave_fft_inv(cplx<T> (&v)[P], cplx<T>* reg,
+                                             const cplx<T>* __restrict__ twl, int lane) {
+  if constexpr (P == 32) wave_inv_pair<T>(v, lane);
+  wave_fft_inv_core<T, P>(v, reg, twl, lane);
 }
 
 }  // namespace bem
