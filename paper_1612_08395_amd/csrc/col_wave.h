@@ -19,6 +19,15 @@
 
 namespace bem {
 
+// Column cc of a workgroup's group is staged in the even region 2 cc, offset
+// by 8 cc elements: the regions are a multiple of 32 banks apart, and the
+// staging copy hands adjacent lanes adjacent columns of one row, which
+// without the offset would all hit the same bank.
+template <int P>
+__device__ __forceinline__ int col_stage_base(int cc) {
+  return 2 * cc * wave_region<P>() + 8 * cc;
+}
+
 template <int LY, int NC>
 __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict__ S, int lx,
                                                          int ny, const float* __restrict__ KT,
@@ -29,6 +38,7 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   constexpr int P = LY / 64;
   constexpr int REG = wave_region<P>();
   constexpr int NT = 128 * NC;
+  static_assert(LY + 8 * (NC - 1) <= REG, "staged column fits its region");
   __shared__ cplx<float> lds[2 * NC * REG];
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -43,12 +53,12 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
     Stage st;
     st.load(S, lx, ny, c0);
 #pragma unroll
-    for (int j = 0; j < Stage::CNT; ++j) lds[(2 * Stage::col(j)) * REG + Stage::row(j)] = st.x[j];
+    for (int j = 0; j < Stage::CNT; ++j) lds[col_stage_base<P>(Stage::col(j)) + Stage::row(j)] = st.x[j];
   }
   __syncthreads();
   // (2) time layout
   cplx<float> v[P];
-  const cplx<float>* src = lds + (2 * jc) * REG;
+  const cplx<float>* src = lds + col_stage_base<P>(jc);
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = src[lane + 64 * m];
   __syncthreads();
@@ -162,14 +172,15 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   __syncthreads();
   if (!parity) {
     const cplx<float>* o = reg + REG;
+    cplx<float>* dst = lds + col_stage_base<P>(jc);
 #pragma unroll
-    for (int m = 0; m < P; ++m) reg[lane + 64 * m] = cadd(v[m], o[lane + 64 * m]);
+    for (int m = 0; m < P; ++m) dst[lane + 64 * m] = cadd(v[m], o[lane + 64 * m]);
   }
   __syncthreads();
   // (7) all LDS reads of the thread, then the stores of rows < ny
   cplx<float> y[Stage::CNT];
 #pragma unroll
-  for (int j = 0; j < Stage::CNT; ++j) y[j] = lds[(2 * Stage::col(j)) * REG + Stage::row(j)];
+  for (int j = 0; j < Stage::CNT; ++j) y[j] = lds[col_stage_base<P>(Stage::col(j)) + Stage::row(j)];
 #pragma unroll
   for (int j = 0; j < Stage::CNT; ++j)
     if (Stage::row(j) < ny) S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
@@ -195,6 +206,7 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
   constexpr int P = LY / 64;
   constexpr int REG = wave_region<P>();
   constexpr int NT = 128 * NC;
+  static_assert(LY + 8 * (NC - 1) <= REG, "staged column fits its region");
   __shared__ cplx<float> lds[2 * NC * REG];
   __shared__ double red[NT / 64];
   if (done && *done) return;
@@ -208,11 +220,11 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
     Stage st;
     st.load(S, lx, ny, c0);
 #pragma unroll
-    for (int j = 0; j < Stage::CNT; ++j) lds[(2 * Stage::col(j)) * REG + Stage::row(j)] = st.x[j];
+    for (int j = 0; j < Stage::CNT; ++j) lds[col_stage_base<P>(Stage::col(j)) + Stage::row(j)] = st.x[j];
   }
   __syncthreads();
   cplx<float> v[P];
-  const cplx<float>* src = lds + (2 * jc) * REG;
+  const cplx<float>* src = lds + col_stage_base<P>(jc);
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = src[lane + 64 * m];
   __syncthreads();
