@@ -28,6 +28,47 @@ __device__ __forceinline__ int col_stage_base(int cc) {
   return 2 * cc * wave_region<P>() + 8 * cc;
 }
 
+// The forward lane-pair step, the multiplication by the real kernel weights
+// and the inverse lane-pair step of a P = 32 wave FFT, in one exchange.
+// Lane (k1, h), register r holds E (h = 0) or O (h = 1) of frequencies f_lo =
+// k1 + 32 r and f_hi = f_lo + 1024; with w = w_64^r and K_lo, K_hi the
+// weights there,
+//   X_lo = E + w O, X_hi = E - w O,  Y = K X,
+//   h = 0 keeps Y_lo + Y_hi        = A E + D (w O),
+//   h = 1 keeps (Y_lo - Y_hi) w^-1 = A O + D (conj(w) E),
+// A = K_lo + K_hi, D = K_lo - K_hi: each lane needs its partner's value and
+// weight only.  The weight of register r is Kc[kq + r dk].
+__device__ __forceinline__ void pair_multiply_pair(cplx<float> (&v)[32],
+                                                   const float* __restrict__ Kc, int kq, int dk,
+                                                   int lane) {
+  const float sg = (lane & 1) ? -1.f : 1.f;
+  // all weights in flight at once (loaded inside the loop below, each would
+  // be waited for before the next is issued)
+  float kw[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    kw[r] = Kc[kq];
+    kq += dk;
+  }
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const float ko = kw[r];
+    const float kp = lane_xor1(ko);
+    const float A = ko + kp, D = sg * (ko - kp);
+    const cplx<float> b = {lane_xor1(v[r].x), lane_xor1(v[r].y)};
+    // b w (h = 0) or b conj(w) (h = 1), w = exp(-2 pi i r / 64)
+    cplx<float> tb = b;
+    const int t = 2 * r;
+    if (t == 32) {
+      tb = {sg * b.y, -sg * b.x};
+    } else if (t != 0) {
+      const float cs = (float)cos128(t), sn = sg * (float)(-sin128(t));
+      tb = {b.x * cs - b.y * sn, b.x * sn + b.y * cs};
+    }
+    v[r] = {A * v[r].x + D * tb.x, A * v[r].y + D * tb.y};
+  }
+}
+
 template <int LY, int NC>
 __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict__ S, int lx,
                                                          int ny, const float* __restrict__ KT,
@@ -71,46 +112,11 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   // (4) spectrum multiply; K(ky) is even: K(ky) = K(2 LY - ky)
   if constexpr (P == 32) {
     if (c != 0) {
-      // The forward lane-pair step, the multiply and the inverse lane-pair
-      // step in one exchange.  Lane (k1, h), register r holds E (h = 0) or O
-      // (h = 1) of frequencies f_lo = k1 + 32 r and f_hi = f_lo + 1024; with
-      // w = w_64^r and K_lo, K_hi the kernel spectrum there,
-      //   X_lo = E + w O, X_hi = E - w O,  Y = K X,
-      //   h = 0 keeps Y_lo + Y_hi        = A E + D (w O),
-      //   h = 1 keeps (Y_lo - Y_hi) w^-1 = A O + D (conj(w) E),
-      // A = K_lo + K_hi, D = K_lo - K_hi: each lane needs its partner's
-      // value and kernel weight only.  The folded spectrum index runs as
-      // kq0 + 64 r (h = 0) or kq0 - 64 r (h = 1).
-      const float* Kc = KT + (size_t)c * kpitch;
+      // lane (k1, h): the folded spectrum index runs as kq0 + 64 r (h = 0)
+      // or kq0 - 64 r (h = 1)
       const int k1 = lane >> 1, h = lane & 1;
-      const float sg = h ? -1.f : 1.f;
-      int kq = h ? LY - 2 * k1 - parity : 2 * k1 + parity;
-      const int dk = h ? -64 : 64;
-      // all weights in flight at once (loaded inside the loop below, each
-      // would be waited for before the next is issued)
-      float kw[P];
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        kw[r] = Kc[kq];
-        kq += dk;
-      }
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        const float ko = kw[r];
-        const float kp = lane_xor1(ko);
-        const float A = ko + kp, D = sg * (ko - kp);
-        const cplx<float> b = {lane_xor1(v[r].x), lane_xor1(v[r].y)};
-        // b w (h = 0) or b conj(w) (h = 1), w = exp(-2 pi i r / 64)
-        cplx<float> tb = b;
-        const int t = 2 * r;
-        if (t == 32) {
-          tb = {sg * b.y, -sg * b.x};
-        } else if (t != 0) {
-          const float cs = (float)cos128(t), sn = sg * (float)(-sin128(t));
-          tb = {b.x * cs - b.y * sn, b.x * sn + b.y * cs};
-        }
-        v[r] = {A * v[r].x + D * tb.x, A * v[r].y + D * tb.y};
-      }
+      pair_multiply_pair(v, KT + (size_t)c * kpitch, h ? LY - 2 * k1 - parity : 2 * k1 + parity,
+                         h ? -64 : 64, lane);
     } else {
       // packed column 0: Z'[k] = ((K0+K1)/2) Z[k] + ((K0-K1)/2) conj(Z[-k]);
       // bins k and -k of one parity half sit in different lanes, so swap
@@ -274,4 +280,211 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
   if (threadIdx.x == 0) part[blockIdx.x] = e;
 }
 
+// Column sweeps at Ly = 4096 (My = 8192) on the same 2048-point wave FFTs.
+// Each of the two My/2-point halves of the pruned transform (even bins: DFT
+// of x; odd bins: DFT of x w_My^n, n < 4096) is split once more by decimation
+// in frequency into the 2048-point DFTs of
+//   y0[n] = x[n] + x[n + 2048]                 (bins 2 j of the half)
+//   y1[n] = (x[n] - x[n + 2048]) w_4096^n      (bins 2 j + 1),
+// so a column takes four waves: quarter q = 2 half + par transforms y_half
+// of the parity-par half and holds the My-point bins ky = 4 f + 2 half + par
+// (f: its 2048-point frequency).  The inverse runs the same steps backwards;
+// with a, b, c, d the inverse quarters (q = 0, 2, 1, 3) after their
+// twiddles 1, conj(w_4096^n), conj(w_8192^n), conj(w_8192^3n),
+//   out[n]        = a + b + c + d
+//   out[n + 2048] = (a - b) + i (c - d),   n < 2048.
+// The twiddles come from the My-point table (w_4096^n = w_8192^2n) and the
+// wave table of Ly = 4096 read at every other k1.  Two columns per
+// workgroup (eight waves, 133 KB of LDS); column cc is staged in regions
+// 4 cc and 4 cc + 1.
+
+template <int NC>
+__device__ __forceinline__ int quarter_stage_base(int cc) {
+  return 4 * cc * wave_region<32>() + 8 * cc;
+}
+
+// Quarter input for wave (par, half), n = lane + 64 m, from the staged column.
+__device__ __forceinline__ void quarter_input(cplx<float> (&v)[32], const cplx<float>* src,
+                                              const cplx<float>* __restrict__ tw, int lane,
+                                              int par, int half) {
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const int n = lane + 64 * m;
+    cplx<float> xa = src[n], xb = src[n + 2048];
+    if (par) {
+      xa = cmul(xa, tw[n]);
+      xb = cmul(xb, tw[n + 2048]);
+    }
+    v[m] = half ? cmul(csub(xa, xb), tw[2 * n]) : cadd(xa, xb);
+  }
+}
+
+// Packed column 0 (DC in re, Nyquist in im): the partner bin -ky of a bin
+// sits in another wave of the column, so the column's spectrum passes
+// through its four LDS regions in natural order (arr[ky], ky < 8192).  All
+// waves of the workgroup take part in the barriers.
+__device__ __forceinline__ int quarter_bin(int lane, int r, int par, int half) {
+  return 4 * wave_freq<32>(lane, r) + 2 * half + par;
+}
+__device__ __forceinline__ int fold8192(int ky) { return ky <= 4096 ? ky : 8192 - ky; }
+
+template <int NC>
+__global__ __launch_bounds__(256 * NC) void k_col_conv_q(cplx<float>* __restrict__ S, int lx,
+                                                         int ny, const float* __restrict__ KT,
+                                                         int kpitch,
+                                                         const cplx<float>* __restrict__ tw,
+                                                         const cplx<float>* __restrict__ twl,
+                                                         const int* __restrict__ done) {
+  constexpr int LY = 4096, P = 32, REG = wave_region<P>();
+  constexpr int NT = 256 * NC;
+  static_assert(LY + 8 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
+  __shared__ cplx<float> lds[4 * NC * REG];
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jc = wv >> 2, q = wv & 3, par = q & 1, half = q >> 1;
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC;
+  const int c = c0 + jc;
+  cplx<float>* reg = lds + wv * REG;
+  using Stage = ColStage<float, LY, NC, NT>;
+  {
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j)
+      lds[quarter_stage_base<NC>(Stage::col(j)) + Stage::row(j)] = st.x[j];
+  }
+  __syncthreads();
+  cplx<float> v[P];
+  quarter_input(v, lds + quarter_stage_base<NC>(jc), tw, lane, par, half);
+  __syncthreads();   // the regions become transpose space
+  wave_fft_fwd_core<float, P, 128>(v, reg, twl, lane);
+  const int k1 = lane >> 1, h = lane & 1;
+  if (c != 0) {
+    const int kq0 = 4 * k1 + 2 * half + par;
+    pair_multiply_pair(v, KT + (size_t)c * kpitch, h ? LY - kq0 : kq0, h ? -128 : 128, lane);
+  }
+  if (c0 == 0) {
+    cplx<float>* arr = lds + 4 * jc * REG;
+    __syncthreads();   // every forward transpose of the workgroup is done
+    if (c == 0) {
+      wave_fwd_pair<float>(v, lane);
+#pragma unroll
+      for (int r = 0; r < P; ++r) arr[quarter_bin(lane, r, par, half)] = v[r];
+    }
+    __syncthreads();
+    if (c == 0) {
+      const float* K1 = KT + (size_t)lx * kpitch;
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int ky = quarter_bin(lane, r, par, half);
+        const cplx<float> z1 = arr[(8192 - ky) & 8191];
+        const int kq = fold8192(ky);
+        const float a = 0.5f * (KT[kq] + K1[kq]), b = 0.5f * (KT[kq] - K1[kq]);
+        v[r] = {a * v[r].x + b * z1.x, a * v[r].y - b * z1.y};
+      }
+    }
+    __syncthreads();   // before the inverse transposes reuse the regions
+    if (c == 0) wave_inv_pair<float>(v, lane);
+  }
+  wave_fft_inv_core<float, P, 128>(v, reg, twl, lane);
+  // own quarter times its twiddle conj(w_8192^(par n + 2 half n))
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int n = lane + 64 * m;
+    reg[n] = cmulc(v[m], tw[(par + 2 * half) * n]);
+  }
+  __syncthreads();
+  cplx<float> y[Stage::CNT];
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j) {
+    const int cc = Stage::col(j), row = Stage::row(j), nn = row & 2047;
+    const cplx<float>* R = lds + 4 * cc * REG;
+    const cplx<float> a = R[nn], cq = R[REG + nn], b = R[2 * REG + nn], d = R[3 * REG + nn];
+    if (row < 2048) {
+      y[j] = {a.x + b.x + cq.x + d.x, a.y + b.y + cq.y + d.y};
+    } else {
+      // (a - b) + i (c - d)
+      y[j] = {a.x - b.x - (cq.y - d.y), a.y - b.y + (cq.x - d.x)};
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Stage::CNT; ++j)
+    if (Stage::row(j) < ny) S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
+}
+
+// Forward quarter transforms and the spectral energy sum_k KT(k) |T(k)|^2
+// (see k_col_energy).  One FP64 partial per workgroup into part[blockIdx.x].
+template <int NC>
+__global__ __launch_bounds__(256 * NC) void k_col_energy_q(const cplx<float>* __restrict__ S,
+                                                           int lx, int ny,
+                                                           const float* __restrict__ KT,
+                                                           int kpitch,
+                                                           const cplx<float>* __restrict__ tw,
+                                                           const cplx<float>* __restrict__ twl,
+                                                           const int* __restrict__ done,
+                                                           double* __restrict__ part) {
+  constexpr int LY = 4096, P = 32, REG = wave_region<P>();
+  constexpr int NT = 256 * NC;
+  static_assert(LY + 8 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
+  __shared__ cplx<float> lds[4 * NC * REG];
+  __shared__ double red[NT / 64];
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jc = wv >> 2, q = wv & 3, par = q & 1, half = q >> 1;
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC;
+  const int c = c0 + jc;
+  cplx<float>* reg = lds + wv * REG;
+  {
+    using Stage = ColStage<float, LY, NC, NT>;
+    Stage st;
+    st.load(S, lx, ny, c0);
+#pragma unroll
+    for (int j = 0; j < Stage::CNT; ++j)
+      lds[quarter_stage_base<NC>(Stage::col(j)) + Stage::row(j)] = st.x[j];
+  }
+  __syncthreads();
+  cplx<float> v[P];
+  quarter_input(v, lds + quarter_stage_base<NC>(jc), tw, lane, par, half);
+  __syncthreads();
+  wave_fft_fwd_core<float, P, 128>(v, reg, twl, lane);
+  wave_fwd_pair<float>(v, lane);
+  double e = 0.0;
+  const int k1 = lane >> 1, h = lane & 1;
+  if (c != 0) {
+    const float* Kc = KT + (size_t)c * kpitch;
+    const int kq0 = 4 * k1 + 2 * half + par;
+    int kq = h ? LY - kq0 : kq0;
+    const int dk = h ? -128 : 128;
+    float kw[P];   // all weights in flight at once
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      kw[r] = Kc[kq];
+      kq += dk;
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) e += energy_term(v[r], kw[r]);
+  }
+  if (c0 == 0) {
+    cplx<float>* arr = lds + 4 * jc * REG;
+    __syncthreads();
+    if (c == 0) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) arr[quarter_bin(lane, r, par, half)] = v[r];
+    }
+    __syncthreads();
+    if (c == 0) {
+      const float* K1 = KT + (size_t)lx * kpitch;
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int ky = quarter_bin(lane, r, par, half);
+        const int kq = fold8192(ky);
+        e += energy_packed(v[r], arr[(8192 - ky) & 8191], KT[kq], K1[kq]);
+      }
+    }
+  }
+  e = block_sum<NT>(e, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
 }  // namespace bem
+

@@ -63,6 +63,12 @@ hipError_t launch_col(const Geom& g, const SpecView<T>& K, cplx<T>* S, const int
         return hipGetLastError();
       }
     }
+    // Ly = 4096: quarter sequences on the same 2048-point wave FFTs
+    if (col_wave_enabled() && g.Ly == 4096 && g.Lx % 2 == 0) {
+      hipLaunchKernelGGL((k_col_conv_q<2>), dim3(g.Lx / 2), dim3(512), 0, s, S, g.Lx, g.ny, K.KT,
+                         g.kpitch, K.twy, K.twly, done);
+      return hipGetLastError();
+    }
   }
   const int W = col_width<T>(g.Ly, g.Lx);
   return dispatch_L(g.Ly, [&](auto LYc) -> hipError_t {
@@ -104,25 +110,36 @@ hipError_t launch_sweep(const Geom& g, const SpecView<T>& K, int which, const T*
       g, K, S, [&](auto PERc) { return PlainStore<T, decltype(PERc)::value>{u, g.nx}; }, s);
 }
 
-// The wave kernel for FP32 at Ly = 2048 (4 columns per workgroup), else the
-// LDS Stockham kernel with the column width launch_col uses.
+// The wave kernels for FP32 at Ly = 2048 (4 columns per workgroup) and
+// Ly = 4096 (2 columns), else the LDS Stockham kernel with the column width
+// launch_col uses.
 template <typename T>
-static bool energy_wave(const Geom& g) {
-  return std::is_same<T, float>::value && col_wave_enabled() && g.Ly == 2048 && g.Lx % 4 == 0;
+static int energy_wave_width(const Geom& g) {
+  if (!std::is_same<T, float>::value || !col_wave_enabled()) return 0;
+  if (g.Ly == 2048 && g.Lx % 4 == 0) return 4;
+  if (g.Ly == 4096 && g.Lx % 2 == 0) return 2;
+  return 0;
 }
 
 template <typename T>
 int col_energy_blocks(const Geom& g) {
-  return energy_wave<T>(g) ? g.Lx / 4 : g.Lx / col_width<T>(g.Ly, g.Lx);
+  const int w = energy_wave_width<T>(g);
+  return g.Lx / (w ? w : col_width<T>(g.Ly, g.Lx));
 }
 
 template <typename T>
 hipError_t launch_col_energy(const Geom& g, const SpecView<T>& K, const cplx<T>* S,
                              const int* done, double* part, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
-    if (energy_wave<T>(g)) {
+    const int w = energy_wave_width<T>(g);
+    if (w == 4) {
       hipLaunchKernelGGL((k_col_energy_w<2048, 4>), dim3(g.Lx / 4), dim3(512), 0, s, S, g.Lx, g.ny,
                          K.KT, g.kpitch, K.twy, K.twly, done, part);
+      return hipGetLastError();
+    }
+    if (w == 2) {
+      hipLaunchKernelGGL((k_col_energy_q<2>), dim3(g.Lx / 2), dim3(512), 0, s, S, g.Lx, g.ny, K.KT,
+                         g.kpitch, K.twy, K.twly, done, part);
       return hipGetLastError();
     }
   }

@@ -107,13 +107,15 @@ __device__ __forceinline__ void reg_dft(cplx<T> (&v)[P]) {
 
 // v[k1] *= w_L^(lane k1) (DIR = -1) or its conjugate (DIR = +1).  twl is a
 // table laid out [k1][lane]: twl[k1 * 64 + l] = exp(-2 pi i l k1 / L), each
-// entry computed in FP64 and rounded once (coalesced across the wave).
-template <typename T, int P, int DIR>
+// entry computed in FP64 and rounded once (coalesced across the wave).  With
+// KS = 128 the table is that of length 2L, read at every other k1 (the same
+// values: l (2 k1) / 2L = l k1 / L).
+template <typename T, int P, int DIR, int KS = 64>
 __device__ __forceinline__ void twiddle_lk1(cplx<T> (&v)[P], const cplx<T>* __restrict__ twl,
                                             int lane) {
 #pragma unroll
   for (int k1 = 1; k1 < P; ++k1) {
-    const cplx<T> w = twl[k1 * 64 + lane];
+    const cplx<T> w = twl[k1 * KS + lane];
     v[k1] = (DIR < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
   }
 }
@@ -158,12 +160,12 @@ __device__ __forceinline__ int wave_freq(int lane, int r) {
 // Forward transform up to (not including) the lane-pair step of P = 32:
 // register DFT, twiddle, transpose, register DFT.  `reg` is this wave's
 // private LDS region (P * 65).
-template <typename T, int P>
+template <typename T, int P, int KS = 64>
 __device__ __forceinline__ void wave_fft_fwd_core(cplx<T> (&v)[P], cplx<T>* reg,
                                                   const cplx<T>* __restrict__ twl, int lane) {
   static_assert(P == 32 || P == 64, "wave FFT sizes");
   reg_dft<T, P, -1>(v);
-  twiddle_lk1<T, P, -1>(v, twl, lane);
+  twiddle_lk1<T, P, -1, KS>(v, twl, lane);
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) reg[k1 * 65 + lane] = v[k1];
   wave_lds_sync();
@@ -221,7 +223,7 @@ __device__ __forceinline__ void wave_inv_pair(cplx<T> (&v)[32], int lane) {
 
 // Inverse transform after the lane-pair step: register DFT, transpose,
 // conjugate twiddle, register DFT; returns y[lane + 64 m] in v[m].
-template <typename T, int P>
+template <typename T, int P, int KS = 64>
 __device__ __forceinline__ void wave_fft_inv_core(cplx<T> (&v)[P], cplx<T>* reg,
                                                   const cplx<T>* __restrict__ twl, int lane) {
   reg_dft<T, P, +1>(v);
@@ -237,7 +239,7 @@ __device__ __forceinline__ void wave_fft_inv_core(cplx<T> (&v)[P], cplx<T>* reg,
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) v[k1] = reg[k1 * 65 + lane];
   wave_lds_sync();
-  twiddle_lk1<T, P, +1>(v, twl, lane);
+  twiddle_lk1<T, P, +1, KS>(v, twl, lane);
   reg_dft<T, P, +1>(v);
 }
 

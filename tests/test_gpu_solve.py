@@ -85,11 +85,12 @@ def test_ragged_and_degenerate_grids(ny, nx, k, shape):
     K.free()
 
 
-@pytest.mark.parametrize("ny,nx,k", [(41, 1300, 0.3), (32, 2048, 0.2)])
-def test_wide_grids_mixed(ny, nx, k):
+@pytest.mark.parametrize("ny,nx,k", [(41, 1300, 0.3), (32, 2048, 0.2), (2100, 48, 0.1)])
+def test_wide_and_tall_grids_mixed(ny, nx, k):
     # 1024 < nx <= 2048: the row spectrum has 2048 columns, so the mixed loop
     # runs its C2R sweeps on the wave-FFT kernels (ragged nx, odd ny: a row
-    # pair with one row)
+    # pair with one row); 2048 < ny <= 4096: the column sweeps run on the
+    # quarter-sequence wave kernels (Ly = 4096)
     bem = _bem()
     announce("wide-mixed", ny, nx, k)
     nu, L = 0.3, 1.0
