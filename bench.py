@@ -285,6 +285,19 @@ def big_grid(bem, torch, depths_n=5):
     sweep()
     torch.cuda.synchronize()
     clk = bem.bem_clock_stop()
+    # accuracy of the mixed path at the last depth against the FP64 path (cold
+    # solves, untimed): this grid and k = -0.3 sit at the FP32 floor
+    p32 = torch.empty_like(h_dev)
+    p64 = torch.empty_like(h_dev)
+    _, r32 = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=dq, precision=bem.BEM_MIXED),
+                               p_out=p32)
+    _, r64 = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=dq), p_out=p64)
+    torch.cuda.synchronize()
+    acc = {"rel_l2_pressure": float(f"{float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)):.3e}"),
+           "contact_count_rel_diff": float(f"{abs(r32.n_contact - r64.n_contact) / r64.n_contact:.3e}"),
+           "status_mixed": r32.status, "residual_mixed": float(f"{r32.residual:.3e}"),
+           "iters_mixed": r32.iters, "iters_fp64": r64.iters}
+    del p32, p64
     K.free()
     iters = sum(r["iters"] for r in res)
     col_ms = clk.ms[1] / clk.launches[1]
@@ -296,7 +309,8 @@ def big_grid(bem, torch, depths_n=5):
             "loop_GBps_algorithmic": round(100.0 * n * n * iters / t / 1e9, 1),
             "column_us_per_launch": round(col_ms * 1e3, 2),
             "column_GBps_algorithmic": round(col_bytes / (col_ms * 1e-3) / 1e9, 1),
-            "contact_area_final": res[-1]["n_contact"] / float(n * n)}
+            "contact_area_final": res[-1]["n_contact"] / float(n * n),
+            "mixed_vs_fp64_last_depth": acc}
 
 
 def oracle_units(cores, Kq):

@@ -137,9 +137,10 @@ typedef struct {
                         max(d, d_preload) (Section 3.1) */
   double tol;        /* relative tolerance; <= 0: 1e-12 (FP64), 1e-6 (MIXED) */
   int max_iter;      /* CG iteration limit per solve; <= 0: 20000 */
-  int stall_limit;   /* stop after this many iterations without a new smallest
-                        residual (MIXED rounding floor); < 0: never;
-                        0: default (50 for MIXED, never for FP64) */
+  int stall_limit;   /* stop after max(stall_limit, half the iterations so far)
+                        iterations without a new smallest residual (MIXED
+                        rounding floor); < 0: never; 0: default (50 for
+                        MIXED, never for FP64) */
 } bem_params;
 
 /* Fills *prm with the defaults (indentation control, FP64, d = 0, no

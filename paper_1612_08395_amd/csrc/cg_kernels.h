@@ -514,10 +514,13 @@ struct DirPro {
       done = 1;
       status = CG_ST_NOCONV;
     } else if (sc->stall_limit > 0) {
+      // the window grows with the solve: while the contact set still moves,
+      // G can stay above its running minimum for hundreds of iterations far
+      // above the rounding floor (4096^2 grids at k = -0.3)
       if (G < best) {
         best = G;
         stall = 0;
-      } else if (++stall >= sc->stall_limit) {
+      } else if (++stall >= max(sc->stall_limit, it / 2)) {
         done = 1;
         status = CG_ST_FLOOR;
       }

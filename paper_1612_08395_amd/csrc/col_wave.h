@@ -303,19 +303,26 @@ __device__ __forceinline__ int quarter_stage_base(int cc) {
   return 4 * cc * wave_region<32>() + 8 * cc;
 }
 
-// Quarter input for wave (par, half), n = lane + 64 m, from the staged column.
+// Quarter input for wave (par, half), n = lane + 64 m, from the staged column:
+//   par = 0: y0 = xa + xb,              y1 = (xa - xb) w^2n
+//   par = 1: y0 = (xa - i xb) w^n,      y1 = (xa + i xb) w^3n
+// with xa = x[n], xb = x[n + 2048], w = w_8192 (w^2048 = -i folds the odd
+// half's pre-twiddle of xb into the combination), i.e. one twiddle
+// w^((par + 2 half) n) per value.
 __device__ __forceinline__ void quarter_input(cplx<float> (&v)[32], const cplx<float>* src,
                                               const cplx<float>* __restrict__ tw, int lane,
                                               int par, int half) {
+  const int e = par + 2 * half;
 #pragma unroll
   for (int m = 0; m < 32; ++m) {
     const int n = lane + 64 * m;
-    cplx<float> xa = src[n], xb = src[n + 2048];
-    if (par) {
-      xa = cmul(xa, tw[n]);
-      xb = cmul(xb, tw[n + 2048]);
-    }
-    v[m] = half ? cmul(csub(xa, xb), tw[2 * n]) : cadd(xa, xb);
+    const cplx<float> xa = src[n], xb = src[n + 2048];
+    cplx<float> y;
+    if (par == 0)
+      y = half ? csub(xa, xb) : cadd(xa, xb);
+    else
+      y = half ? cplx<float>{xa.x - xb.y, xa.y + xb.x} : cplx<float>{xa.x + xb.y, xa.y - xb.x};
+    v[m] = e ? cmul(y, tw[e * n]) : y;
   }
 }
 
