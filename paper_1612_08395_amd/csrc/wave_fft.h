@@ -25,81 +25,6 @@
 
 namespace bem {
 
-// cos(pi t / 64), t = 0..32
-__host__ __device__ constexpr double cos_q(int t) {
-  constexpr double c[33] = {
-      1.0, 0.9987954562051724, 0.9951847266721969, 0.989176509964781,
-      0.9807852804032304, 0.970031253194544, 0.9569403357322088, 0.9415440651830208,
-      0.9238795325112867, 0.9039892931234433, 0.881921264348355, 0.8577286100002721,
-      0.8314696123025452, 0.8032075314806449, 0.773010453362737, 0.7409511253549591,
-      0.7071067811865476, 0.6715589548470183, 0.6343932841636455, 0.5956993044924335,
-      0.5555702330196023, 0.5141027441932217, 0.4713967368259978, 0.4275550934302822,
-      0.38268343236508984, 0.33688985339222005, 0.29028467725446233, 0.24298017990326398,
-      0.19509032201612833, 0.14673047445536175, 0.09801714032956077, 0.049067674327418126,
-      0.0};
-  return c[t];
-}
-
-// cos / sin of 2 pi t / 128 for any integer t, from the quadrant table
-__host__ __device__ constexpr double cos128(int t) {
-  t &= 127;
-  return t <= 32 ? cos_q(t) : t <= 64 ? -cos_q(64 - t) : t <= 96 ? -cos_q(t - 64) : cos_q(128 - t);
-}
-__host__ __device__ constexpr double sin128(int t) { return cos128(t - 32); }
-
-// y * w_N^j with w_N = exp(DIR 2 pi i / N), N <= 128, N | 128
-template <typename T, int DIR>
-__device__ __forceinline__ cplx<T> mul_wn(cplx<T> y, int j, int N) {
-  const int t = (j * (128 / N)) & 127;
-  if (t == 0) return y;
-  if (t == 64) return {-y.x, -y.y};
-  if (t == 32) return rot90<DIR>(y);
-  if (t == 96) return rot90<-DIR>(y);
-  const T c = (T)cos128(t), s = (T)(DIR * sin128(t));
-  return {y.x * c - y.y * s, y.x * s + y.y * c};
-}
-
-// In-register DFT of N points, natural order in and out, by the split-radix
-// decimation in time: with U the N/2-point DFT of the even samples and Z, Z'
-// the N/4-point DFTs of x[4n + 1] and x[4n + 3],
-//   X[k]          = U[k] + (w^k Z[k] + w^3k Z'[k])
-//   X[k + N/2]    = U[k] - (w^k Z[k] + w^3k Z'[k])
-//   X[k + N/4]    = U[k + N/4] + rot(w^k Z[k] - w^3k Z'[k])
-//   X[k + 3N/4]   = U[k + N/4] - rot(w^k Z[k] - w^3k Z'[k])
-// for k < N/4, w = exp(DIR 2 pi i / N), rot = multiplication by DIR i.
-// Every index is a constant after unrolling; for N = 32 this takes 423
-// VALU instructions against 452 for radix 2.
-template <typename T, int DIR, int N>
-__device__ __forceinline__ void split_radix_dft(cplx<T> (&x)[N]) {
-  if constexpr (N == 2) {
-    dft2<DIR>(x[0], x[1]);
-  } else if constexpr (N == 4) {
-    dft4<DIR>(x);
-  } else if constexpr (N > 4) {
-    cplx<T> u[N / 2], z[N / 4], zp[N / 4];
-#pragma unroll
-    for (int n = 0; n < N / 2; ++n) u[n] = x[2 * n];
-#pragma unroll
-    for (int n = 0; n < N / 4; ++n) {
-      z[n] = x[4 * n + 1];
-      zp[n] = x[4 * n + 3];
-    }
-    split_radix_dft<T, DIR, N / 2>(u);
-    split_radix_dft<T, DIR, N / 4>(z);
-    split_radix_dft<T, DIR, N / 4>(zp);
-#pragma unroll
-    for (int k = 0; k < N / 4; ++k) {
-      const cplx<T> a = mul_wn<T, DIR>(z[k], k, N);
-      const cplx<T> b = mul_wn<T, DIR>(zp[k], 3 * k, N);
-      const cplx<T> sm = cadd(a, b), df = rot90<DIR>(csub(a, b));
-      x[k] = cadd(u[k], sm);
-      x[k + N / 2] = csub(u[k], sm);
-      x[k + N / 4] = cadd(u[k + N / 4], df);
-      x[k + 3 * N / 4] = csub(u[k + N / 4], df);
-    }
-  }
-}
-
 template <typename T, int P, int DIR>
 __device__ __forceinline__ void reg_dft(cplx<T> (&v)[P]) {
   split_radix_dft<T, DIR, P>(v);
