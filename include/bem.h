@@ -230,16 +230,17 @@ int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const d
               int n_steps, bem_state_t state, bem_result* res, void* stream);
 
 /*
- * bem_sweep_dev -- bem_sweep with the gap profile h on the device (ny x nx
- * FP64, read in place, not copied) and the steps split over `chains`
- * (1..8) warm-start chains: chain c solves steps c, c + chains, c + 2 chains,
- * ..., each warm-started from the chain's previous step, and the chains run
+ * bem_sweep_dev -- the indentation sweep of bem_sweep (Sections 2.2, 3.1)
+ * with the gap profile h on the device (ny x nx FP64, read in place, not
+ * copied) and the steps split over `chains` (1..8) warm-start chains: chain
+ * c solves steps c, c + chains, c + 2 chains, ..., each warm-started from
+ * the chain's previous step, and the chains run
  * concurrently on the GPU (chain 0 on `stream` in `state`, chain c > 0 in a
  * state and on a non-blocking stream of its own, after the work already
  * queued on `stream`; one host thread per chain).  Each non-adhesive step
  * has one solution, so the chains change iteration counts, not results
  * (within the tolerance).  Kernels of one chain fill the gaps of another:
- * on a 2048^2 mixed sweep, 2 chains give about 9 % more solves/s than 1.
+ * on a 2048^2 mixed sweep, 2 chains give about 10 % more solves/s than 1.
  * On return, `state` holds the last step's pressure and contact set.
  * chains = 1 is the sequential sweep of bem_sweep (adhesive sweeps, whose
  * pull-off steps depend on the path, need chains = 1: else
