@@ -98,11 +98,18 @@ def test_zero_load_and_force_sweep():
     rc, sweep = bem.bem_sweep(K, h, _force_params(bem, 0.0, bem.BEM_FP64), forces, state=st)
     st.free()
     assert rc == 0
-    for F, r in zip(forces, sweep):
+    # the same loads through the device-h entry point as two concurrent chains
+    import torch
+    h_dev = torch.tensor(h, dtype=torch.float64, device="cuda")
+    rc2, chained = bem.bem_sweep_dev(K, h_dev, _force_params(bem, 0.0, bem.BEM_FP64), forces,
+                                     chains=2)
+    assert rc2 == 0
+    for F, r, r2 in zip(forces, sweep, chained):
         _, cold, _, _, _ = bem.bem_solve(K, h, _force_params(bem, F, bem.BEM_FP64))
-        assert r.F == pytest.approx(F, rel=1e-12)
-        assert r.d == pytest.approx(cold.d, rel=1e-10)
-        assert r.n_contact == cold.n_contact
+        for x in (r, r2):
+            assert x.F == pytest.approx(F, rel=1e-12)
+            assert x.d == pytest.approx(cold.d, rel=1e-10)
+            assert x.n_contact == cold.n_contact
     K.free()
 
 
