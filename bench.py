@@ -502,16 +502,33 @@ def main():
     comp = 20.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
     out["compulsory_GBps"] = round(comp, 1)
     out["compulsory_frac"] = round(comp / HBM_PEAK_GBS, 4)
+    # the remaining legs report beside the headline; a failure in one of them
+    # is recorded in its field (and the exit status) instead of losing the line
+    failed = False
+
+    def leg(key, fn):
+        nonlocal failed
+        try:
+            out[key] = fn()
+        except Exception as e:  # noqa: BLE001
+            failed = True
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] {key} failed: {e}")
+
     if not args.no_big_grid:
         log("[bench] 4096^2 sweep")
-        out["hbm_resident_4096"] = big_grid(bem, torch)
+        leg("hbm_resident_4096", lambda: big_grid(bem, torch))
     if args.serving_requests > 0:
         log("[bench] serving")
-        out["serving"] = serving(args.serving_requests, args.serving_slots, bem)
+        leg("serving", lambda: serving(args.serving_requests, args.serving_slots, bem))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(h, depths, sum(it64) / len(it64), args.cpu_iters)
+        leg("cpu_baseline",
+            lambda: cpu_baseline(h, depths, sum(it64) / len(it64), args.cpu_iters))
     print(json.dumps(out), flush=True)
+    if failed:
+        K.free()
+        return 1
     K.free()
     return 0
 

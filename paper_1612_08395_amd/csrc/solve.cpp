@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -698,8 +699,9 @@ int bem_sweep_dev(bem_influence_t K, const double* h, const bem_params* prm, con
   if (rc == BEM_OK) {
     std::vector<int> rcs(chains, BEM_OK);
     std::vector<std::string> msgs(chains);
+    const std::thread::id caller = std::this_thread::get_id();
     auto run = [&](int c) {
-      if (c > 0) (void)hipSetDevice(K->device);
+      if (std::this_thread::get_id() != caller) (void)hipSetDevice(K->device);
       rcs[c] = sweep_steps(K, h, prm, d_list, n_steps, c, chains, st[c], res, ss[c]);
       if (rcs[c] < 0) msgs[c] = bem_last_error();
       const hipError_t es = hipStreamSynchronize(ss[c]);
@@ -708,9 +710,18 @@ int bem_sweep_dev(bem_influence_t K, const double* h, const bem_params* prm, con
         msgs[c] = std::string("bem_sweep_dev: ") + hipGetErrorString(es);
       }
     };
+    // a chain whose thread cannot be started runs on this thread afterwards
     std::vector<std::thread> workers;
-    for (int c = 1; c < chains; ++c) workers.emplace_back(run, c);
+    std::vector<int> inline_chains;
+    for (int c = 1; c < chains; ++c) {
+      try {
+        workers.emplace_back(run, c);
+      } catch (const std::system_error&) {
+        inline_chains.push_back(c);
+      }
+    }
     run(0);
+    for (const int c : inline_chains) run(c);
     for (auto& w : workers) w.join();
     int worst = BEM_OK;
     const char* msg = nullptr;
