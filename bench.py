@@ -99,6 +99,13 @@ def sweep_dev(bem, K, h_dev, depths, precision, chains):
     return [r.as_dict() for r in res]
 
 
+def loop_bytes(f):
+    """Algorithmic bytes per grid element of one FP32 CG iteration at contact
+    fraction f: update + R2C 24 - 4 (1 - f), column sweep 20, C2R + gap 20,
+    direction + R2C 24 - 8 (1 - f), column energy 12."""
+    return 88.0 + 12.0 * f
+
+
 def timed(bem, K, h_dev, depths, precision, steps, warmup, torch, chains, clock=True):
     """Times `steps` sweeps, uninstrumented.  Then (clock=True) one more sweep
     of the same depths runs as a single chain with the library's solver clock
@@ -306,7 +313,8 @@ def big_grid(bem, torch, depths_n=5):
             "depths": depths_n, "d_max": dq, "solves_per_s": round(depths_n / t, 3),
             "iters_per_solve": round(iters / depths_n, 2),
             "loop_us_per_iteration": round(sum(clk.ms) / clk.iterations * 1e3, 2),
-            "loop_GBps_algorithmic": round(100.0 * n * n * iters / t / 1e9, 1),
+            "loop_GBps_algorithmic": round(sum(loop_bytes(r["n_contact"] / (n * n)) * n * n
+                                               * r["iters"] for r in res) / t / 1e9, 1),
             "column_us_per_launch": round(col_ms * 1e3, 2),
             "column_GBps_algorithmic": round(col_bytes / (col_ms * 1e-3) / 1e9, 1),
             "contact_area_final": res[-1]["n_contact"] / float(n * n),
@@ -460,10 +468,14 @@ def main():
     solves32 = N_DEPTHS * args.steps / t32
     solves64 = N_DEPTHS * args.fp64_steps / t64
     ms_step = t32 / args.steps * 1e3
-    # whole-loop effective bandwidth: 100 algorithmic bytes per element per CG
-    # iteration (FP32 path, five launches), 200 for FP64
-    loop32 = 100.0 * N * N * sum(it32) / (t32 / args.steps) / 1e9
-    loop64 = 200.0 * N * N * sum(it64) / (t64 / args.fp64_steps) / 1e9
+    # whole-loop effective bandwidth: algorithmic bytes per element per CG
+    # iteration (FP32 path, five launches) 88 + 12 f, with f the contact
+    # fraction (the direction and update prologues read t and g only in the
+    # contact set), twice that for FP64; f of each solve's final contact set
+    loop32 = sum(loop_bytes(x["n_contact"] / (N * N)) * N * N * x["iters"]
+                 for x in res32[-1]) / (t32 / args.steps) / 1e9
+    loop64 = sum(2 * loop_bytes(x["n_contact"] / (N * N)) * N * N * x["iters"]
+                 for x in res64[-1]) / (t64 / args.fp64_steps) / 1e9
 
     log("[bench] roofline")
     roof = roofline(bem, K, clk32, torch)
