@@ -99,11 +99,14 @@ def sweep_dev(bem, K, h_dev, depths, precision, chains):
     return [r.as_dict() for r in res]
 
 
-def loop_bytes(f):
-    """Algorithmic bytes per grid element of one FP32 CG iteration at contact
-    fraction f: update + R2C 24 - 4 (1 - f), column sweep 20, C2R + gap 20,
-    direction + R2C 24 - 8 (1 - f), column energy 12."""
-    return 88.0 + 12.0 * f
+def loop_bytes(f, w=4):
+    """Algorithmic bytes per grid element of one CG iteration at contact
+    fraction f, for w-byte reals (4 FP32, 8 FP64).  In FP32: update + R2C
+    21 + 4 f (p, g, flags, spectrum; t on the contact set), column sweep 20,
+    C2R + gap 17, direction + R2C 13 + 8 f (flags, t, spectrum; g and t on
+    the contact set), column energy 12: 83 + 12 f.  The contact flags are 3
+    of those bytes and stay one byte per element in FP64."""
+    return (80.0 + 12.0 * f) * w / 4 + 3.0
 
 
 def timed(bem, K, h_dev, depths, precision, steps, warmup, torch, chains, clock=True):
@@ -469,12 +472,12 @@ def main():
     solves64 = N_DEPTHS * args.fp64_steps / t64
     ms_step = t32 / args.steps * 1e3
     # whole-loop effective bandwidth: algorithmic bytes per element per CG
-    # iteration (FP32 path, five launches) 88 + 12 f, with f the contact
+    # iteration (five launches) 83 + 12 f in FP32, with f the contact
     # fraction (the direction and update prologues read t and g only in the
-    # contact set), twice that for FP64; f of each solve's final contact set
+    # contact set), 163 + 24 f in FP64; f of each solve's final contact set
     loop32 = sum(loop_bytes(x["n_contact"] / (N * N)) * N * N * x["iters"]
                  for x in res32[-1]) / (t32 / args.steps) / 1e9
-    loop64 = sum(2 * loop_bytes(x["n_contact"] / (N * N)) * N * N * x["iters"]
+    loop64 = sum(loop_bytes(x["n_contact"] / (N * N), 8) * N * N * x["iters"]
                  for x in res64[-1]) / (t64 / args.fp64_steps) / 1e9
 
     log("[bench] roofline")

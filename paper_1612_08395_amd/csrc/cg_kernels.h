@@ -217,7 +217,7 @@ struct UpdatePro {
   T* p;
   const T* t;
   const T* g;
-  const uint8_t* mask;
+  uint8_t* mask;         // fixed set: the set A (read); else Ic = {p > 0} (written)
   const CgScal* sc;
   double* part;
   int nx, nb, it;
@@ -339,6 +339,11 @@ struct UpdatePro {
       if (n < nxl) {
         p[(size_t)ya * nx + n] = va[q];
         if (hasb) p[(size_t)yb * nx + n] = vb[q];
+        if constexpr (!FS) {
+          // contact flags for the rest of the iteration (1 byte instead of p)
+          mask[(size_t)ya * nx + n] = va[q] > T(0) ? 1 : 0;
+          if (hasb) mask[(size_t)yb * nx + n] = vb[q] > T(0) ? 1 : 0;
+        }
       }
     }
   }
@@ -383,13 +388,9 @@ struct GapEpi {
       const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
       ha[q] = load_or0(hd, a, sf, in);
       hb[q] = load_or0(hd, b, sf, inb);
-      if constexpr (FS) {
-        ca[q] = load_or0(mask, a, sf, in) != 0;
-        cb[q] = load_or0(mask, b, sf, inb) != 0;
-      } else {
-        ca[q] = load_or0(p, a, sf, in) > T(0);
-        cb[q] = load_or0(p, b, sf, inb) > T(0);
-      }
+      // Ic: the fixed set A, or the flags {p > 0} the update kept current
+      ca[q] = load_or0(mask, a, sf, in) != 0;
+      cb[q] = load_or0(mask, b, sf, inb) != 0;
     }
   }
   // after the loads are issued: the reductions the epilogue needs
@@ -470,7 +471,7 @@ struct DirPro {
   }
   // The contact flags first; g and t only where an element is in Ic (t is 0
   // elsewhere): off Ic a lane reads its row's first element instead, one
-  // cache line per wave, which cuts the field reads from 12 to about 4 +
+  // cache line per wave, which cuts the field reads from 12 to about 1 +
   // 8 x (contact fraction) bytes per element.
   template <int NTHR>
   __device__ void fetch(int ya, int yb, bool hasb, int nxl) {
@@ -479,13 +480,9 @@ struct DirPro {
       const int n = threadIdx.x + q * NTHR;
       const bool in = n < nxl, inb = in && hasb;
       const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
-      if constexpr (FS) {
-        ca[q] = load_or0(mask, a, sf, in) != 0;
-        cb[q] = load_or0(mask, b, sf, inb) != 0;
-      } else {
-        ca[q] = load_or0(p, a, sf, in) > T(0);
-        cb[q] = load_or0(p, b, sf, inb) > T(0);
-      }
+      // Ic: the fixed set A, or the flags {p > 0} the update kept current
+      ca[q] = load_or0(mask, a, sf, in) != 0;
+      cb[q] = load_or0(mask, b, sf, inb) != 0;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -609,7 +606,7 @@ struct DotsEpi {
   static constexpr int NV = FC ? 4 : 2;
   const T* g;
   const T* t;
-  const T* p;
+  const uint8_t* mask;   // Ic = {p > 0}, kept current by UpdatePro
   const CgScal* sc;
   double* part;
   int nx, it;
@@ -625,20 +622,24 @@ struct DotsEpi {
   }
   template <int NTHR>
   __device__ void prefetch(int ya, int yb, bool hasb, int nxl) {
+    // the flags first, then g and t on Ic only (t is 0 elsewhere, so every
+    // sum is over Ic)
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       const bool in = n < nxl, inb = in && hasb;
       const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
-      ga_[q] = load_or0(g, a, sf, in);
-      ta_[q] = load_or0(t, a, sf, in);
-      gb_[q] = load_or0(g, b, sf, inb);
-      tb_[q] = load_or0(t, b, sf, inb);
-      ca[q] = cb[q] = false;
-      if constexpr (FC) {
-        ca[q] = load_or0(p, a, sf, in) > T(0);
-        cb[q] = load_or0(p, b, sf, inb) > T(0);
-      }
+      ca[q] = load_or0(mask, a, sf, in) != 0;
+      cb[q] = load_or0(mask, b, sf, inb) != 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int n = threadIdx.x + q * NTHR;
+      const size_t a = (size_t)ya * nx + n, b = (size_t)yb * nx + n, sf = (size_t)ya * nx;
+      ga_[q] = load_or0(g, a, sf, ca[q]);
+      ta_[q] = load_or0(t, a, sf, ca[q]);
+      gb_[q] = load_or0(g, b, sf, cb[q]);
+      tb_[q] = load_or0(t, b, sf, cb[q]);
     }
   }
   template <int NTHR>
@@ -691,13 +692,19 @@ __global__ __launch_bounds__(EW_THREADS) void k_cold_start(T* __restrict__ p, co
 // non-adhesive mode: clip a warm-start pressure to p >= 0.
 template <typename T>
 __global__ __launch_bounds__(EW_THREADS) void k_prepare(T* __restrict__ t, T* __restrict__ p,
-                                                        const uint8_t* __restrict__ mask, int clip,
+                                                        uint8_t* __restrict__ mask, int fixed_set,
                                                         size_t n) {
   for (size_t i = blockIdx.x * (size_t)EW_THREADS + threadIdx.x; i < n;
        i += (size_t)gridDim.x * EW_THREADS) {
     t[i] = T(0);
-    if (mask && !mask[i]) p[i] = T(0);
-    if (clip && p[i] < T(0)) p[i] = T(0);
+    if (fixed_set) {
+      if (!mask[i]) p[i] = T(0);
+    } else {
+      // the loop's contact flags: Ic = {p > 0}, kept current by UpdatePro
+      T pv = p[i];
+      if (pv < T(0)) p[i] = pv = T(0);
+      mask[i] = pv > T(0) ? 1 : 0;
+    }
   }
 }
 

@@ -78,7 +78,8 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
     e = launch_row_c2r<T, false>(
         g, K, b.S,
         [&](auto PERc) {
-          return DotsEpi<T, MODE, decltype(PERc)::value>{b.g, b.t, b.p, b.sc, b.part, g.nx, it};
+          return DotsEpi<T, MODE, decltype(PERc)::value>{b.g, b.t, b.mask, b.sc, b.part, g.nx,
+                                                          it};
         },
         s);
     if (e != hipSuccess) return e;
@@ -120,9 +121,9 @@ hipError_t launch_cold_start(T* p, const T* hd, double inv_ck00, size_t n, hipSt
 }
 
 template <typename T>
-hipError_t launch_prepare(T* t, T* p, const uint8_t* mask, bool clip, size_t n, hipStream_t s) {
+hipError_t launch_prepare(T* t, T* p, uint8_t* mask, bool fixed_set, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, s, t, p, mask,
-                     clip ? 1 : 0, n);
+                     fixed_set ? 1 : 0, n);
   return hipGetLastError();
 }
 
@@ -185,7 +186,7 @@ hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, s
   template hipError_t launch_min_h<T>(const double*, size_t, CgScal*, hipStream_t);              \
   template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \
   template hipError_t launch_cold_start<T>(T*, const T*, double, size_t, hipStream_t);           \
-  template hipError_t launch_prepare<T>(T*, T*, const uint8_t*, bool, size_t, hipStream_t);      \
+  template hipError_t launch_prepare<T>(T*, T*, uint8_t*, bool, size_t, hipStream_t);            \
   template hipError_t launch_finalize<T>(const CgBufs<T>&, int, size_t, hipStream_t);           \
   template hipError_t launch_detach<T>(const CgBufs<T>&, double, size_t, hipStream_t);          \
   template hipError_t launch_to_f64<T>(const T*, double*, size_t, hipStream_t);                  \

@@ -135,8 +135,7 @@ int run_cg(bem_state_s* st, int mode, const SolveCfg& cfg, int* iters, double* r
   h->W = cfg.W;
   hipError_t e = hipMemcpyAsync(st->sc, h, sizeof(CgScal), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "solver scalars");
-  if ((e = launch_prepare<T>((T*)st->t, (T*)st->p, fixed_set ? st->mask : nullptr, !fixed_set,
-                             st->n, s)) != hipSuccess)
+  if ((e = launch_prepare<T>((T*)st->t, (T*)st->p, st->mask, fixed_set, st->n, s)) != hipSuccess)
     return hip_fail(e, "solver prepare");
   const Geom& g = st->K->g;
   const SpecView<T> K = spec_view<T>(st->K);
