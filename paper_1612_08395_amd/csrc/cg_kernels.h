@@ -450,6 +450,10 @@ template <typename T, int MODE, int PER>
 struct DirPro {
   static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
   static constexpr int NVG = FC ? 4 : 2;
+  // at L = 4096 the uncapped kernel takes 130 VGPRs (3 waves per SIMD, one
+  // 8-wave workgroup per CU); capped at 128 it does not spill, except under
+  // load control, which keeps the compiler's choice
+  static constexpr int kMinWaves = FC ? 1 : 4;
   T* t;
   const T* g;
   const T* p;

@@ -31,6 +31,8 @@
 // state there), an epilogue consumes u at (y, x).  Both may accumulate FP64
 // partial sums; finish() reduces them per workgroup.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "fft_lds.h"
 
@@ -114,8 +116,21 @@ struct PlainStore {
 template <int L, int NTHR>
 __host__ __device__ constexpr int row_per() { return (L + NTHR - 1) / NTHR; }
 
+// Waves per SIMD a row sweep asks the compiler to leave room for: a
+// prologue may set kMinWaves (else 1, no register cap).  With 8-wave
+// workgroups (L = 4096), 4 waves per SIMD (at most 128 VGPRs) is what lets
+// two workgroups share a CU, as their LDS allows.
+template <class F, class = void>
+struct min_waves_of {
+  static constexpr int value = 1;
+};
+template <class F>
+struct min_waves_of<F, std::void_t<decltype(F::kMinWaves)>> {
+  static constexpr int value = F::kMinWaves;
+};
+
 template <typename T, int L, int NTHR, class Pro>
-__global__ __launch_bounds__(NTHR) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
+__global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
                                                   int ny, const cplx<T>* __restrict__ tw) {
   constexpr int STR = lds_len(L);
   constexpr int PER = row_per<L, NTHR>();
