@@ -110,6 +110,45 @@ def test_wide_and_tall_grids_mixed(ny, nx, k):
     K.free()
 
 
+def test_rows_longer_than_2048():
+    # 2048 < nx <= 4096: the CG loop runs 4096-point row transforms (Stockham,
+    # 512 threads a row pair, the direction prologue held to 128 VGPRs).
+    # Displacement-controlled solves in both precisions, then one pull-off
+    # step with adhesion (fixed-set solves; gamma chosen so that one detach
+    # round takes 4 elements out of the contact set).
+    bem = _bem()
+    ny, nx, k, nu, L, gam = 24, 2200, -0.3, 0.25, 1.0, 2.5e-4
+    announce("long-rows", ny, nx, k)
+    dx = L / nx
+    Kq = inf.influence_quarter(nx, ny, dx, dx, k)
+    C = m.compliance(k, nu)
+    conv = FFTConvolver(Kq, C, workers=-1)
+    xs = (np.arange(nx) + 0.5) * dx - 0.5 * L
+    ys = (np.arange(ny) + 0.5) * dx - 0.5 * ny * dx
+    h = (xs[None, :] ** 2 + 4.0 * ys[:, None] ** 2) / 2.0
+    d0 = float(np.quantile(h, 0.3))
+    ref = so.solve_nonadhesive(Kq, C, h, d0, tol=1e-12, conv=conv)
+    K = bem.bem_influence(nx, ny, dx, k, nu)
+    _, rm, pm, cm, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d0, precision=bem.BEM_MIXED))
+    assert rm.status in (0, bem.BEM_EFLOOR)
+    assert rel_l2(pm, ref.p) <= MIXED_TOL
+    assert _count_close(rm.n_contact, ref.contact.sum())
+    st = bem.bem_state_create(K)
+    _, r64, p64, c64, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d0), state=st)
+    assert rel_l2(p64, ref.p) <= FP64_TOL
+    assert np.array_equal(c64.astype(bool), ref.contact)
+    d1 = 0.8 * d0
+    step = so.adhesive_step(Kq, C, h, d1, ref.contact, ref.p, m.p_crit(k, nu, gam, dx),
+                            tol=1e-12, conv=conv)
+    assert step.rounds == 1 and step.contact.sum() == ref.contact.sum() - 4
+    _, ra, pa, ca, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d1, gamma=gam), state=st)
+    assert ra.detach_rounds == step.rounds
+    assert np.array_equal(ca.astype(bool), step.contact)
+    assert rel_l2(pa, step.p) <= FP64_TOL
+    st.free()
+    K.free()
+
+
 def test_no_contact_and_full_contact():
     bem = _bem()
     announce("degenerate-contact")
