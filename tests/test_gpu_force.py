@@ -31,6 +31,7 @@ CASES = [
     (64, 64, 1.0, 0.3, "parabolic", 2e-3),
     (37, 50, 1.0, -0.5, "parabolic", 1.5e-3),      # ragged, non-square grid
     (96, 96, 1.0, 0.2, "rough", None),              # force from a 5 % quantile depth
+    (2200, 24, 1.0, -0.3, "parabolic", None),       # 4096-point row transforms
 ]
 
 
