@@ -9,7 +9,7 @@
 // keeps the data in registers apart from one transpose, so the transform
 // costs about half the VALU and LDS work.
 //
-// LDS: one region of P x 65 complex values per wave.  The row pair passes
+// LDS: one region of P x 66 complex values per wave.  The row pair passes
 // through region 0 in natural order on the way in (R2C) or out (C2R); each
 // wave's spectrum half sits in its own region in natural frequency order for
 // the untangling (R2C) or the Hermitian completion (C2R).  The prologue /

@@ -61,9 +61,17 @@ __device__ __forceinline__ double lane_xor1(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// LDS words per wave region (complex elements): P rows of 64 + 1 padding
+// Row pitch (complex elements) of a wave's transpose region: 64 values and
+// padding.  For P = 32 the transposed access (lane (k1, h) at row k1, column
+// 2 i + h) spreads a half-wave over distinct banks only with a pitch of 66
+// (132 dwords, 4 mod 32); with 65 the lanes (k1, 1) and (k1 + 1, 0) share
+// banks.  For P = 64 (lane l at row l) 65 suffices.
 template <int P>
-__host__ __device__ constexpr int wave_region() { return P * 65; }
+__host__ __device__ constexpr int wave_pitch() { return P == 32 ? 66 : 65; }
+
+// LDS words per wave region (complex elements): P rows of wave_pitch
+template <int P>
+__host__ __device__ constexpr int wave_region() { return P * wave_pitch<P>(); }
 
 // The transpose regions are private to a wave, so a wave-level ordering
 // point suffices between writing a region and reading other lanes' values:
@@ -84,23 +92,24 @@ __device__ __forceinline__ int wave_freq(int lane, int r) {
 
 // Forward transform up to (not including) the lane-pair step of P = 32:
 // register DFT, twiddle, transpose, register DFT.  `reg` is this wave's
-// private LDS region (P * 65).
+// private LDS region (wave_region<P>()).
 template <typename T, int P, int KS = 64>
 __device__ __forceinline__ void wave_fft_fwd_core(cplx<T> (&v)[P], cplx<T>* reg,
                                                   const cplx<T>* __restrict__ twl, int lane) {
   static_assert(P == 32 || P == 64, "wave FFT sizes");
+  constexpr int PT = wave_pitch<P>();
   reg_dft<T, P, -1>(v);
   twiddle_lk1<T, P, -1, KS>(v, twl, lane);
 #pragma unroll
-  for (int k1 = 0; k1 < P; ++k1) reg[k1 * 65 + lane] = v[k1];
+  for (int k1 = 0; k1 < P; ++k1) reg[k1 * PT + lane] = v[k1];
   wave_lds_sync();
   if constexpr (P == 32) {
     const int k1 = lane >> 1, h = lane & 1;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = reg[k1 * 65 + 2 * i + h];
+    for (int i = 0; i < 32; ++i) v[i] = reg[k1 * PT + 2 * i + h];
   } else {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = reg[lane * 65 + i];
+    for (int i = 0; i < 64; ++i) v[i] = reg[lane * PT + i];
   }
   wave_lds_sync();
   reg_dft<T, P, -1>(v);
@@ -151,18 +160,19 @@ __device__ __forceinline__ void wave_inv_pair(cplx<T> (&v)[32], int lane) {
 template <typename T, int P, int KS = 64>
 __device__ __forceinline__ void wave_fft_inv_core(cplx<T> (&v)[P], cplx<T>* reg,
                                                   const cplx<T>* __restrict__ twl, int lane) {
+  constexpr int PT = wave_pitch<P>();
   reg_dft<T, P, +1>(v);
   if constexpr (P == 32) {
     const int k1 = lane >> 1, h = lane & 1;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) reg[k1 * 65 + 2 * i + h] = v[i];
+    for (int i = 0; i < 32; ++i) reg[k1 * PT + 2 * i + h] = v[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) reg[lane * 65 + i] = v[i];
+    for (int i = 0; i < 64; ++i) reg[lane * PT + i] = v[i];
   }
   wave_lds_sync();
 #pragma unroll
-  for (int k1 = 0; k1 < P; ++k1) v[k1] = reg[k1 * 65 + lane];
+  for (int k1 = 0; k1 < P; ++k1) v[k1] = reg[k1 * PT + lane];
   wave_lds_sync();
   twiddle_lk1<T, P, +1, KS>(v, twl, lane);
   reg_dft<T, P, +1>(v);
