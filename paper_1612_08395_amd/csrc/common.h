@@ -40,8 +40,39 @@ __device__ __forceinline__ T load_or0(const T* __restrict__ a, size_t i, size_t 
   return ok ? v : T(0);
 }
 
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 5) + 1; }
+// Layout of a sequence in LDS for the Stockham passes (element i of a
+// sequence sits at idx(i); sequences are stride apart).  LDS serves a 64-bit
+// access 32 lanes at a time over 64 banks, a 128-bit access 16 lanes at a
+// time.  join(idx(a), idx(b)) = idx(a | b) when a and b share no bits, which
+// the passes use to address a butterfly's R points from one base.
+//  FP32: one padding element per 32 (join is an addition, so the R points
+//   share one address register with immediate offsets).
+//  FP64: an XOR swizzle, i with bits 4 and 5 (5 and 6, ...) folded into its
+//   low 4 bits: a permutation of every power-of-two length, linear over
+//   GF(2).  The radix-8/4 passes at 2048 and 4096 points then hit 1.125
+//   lanes per bank on average instead of 1.5 with padding (measured: FP64
+//   column sweep at 2048^2 125 -> 118 us); for FP32 the XOR addressing costs
+//   more VALU than the conflicts it removes (1.375 -> 1.125).
+//  The stride offsets put the halves of a row pair or adjacent staged
+//  columns on different banks.
+template <typename T>
+struct LdsLayout;
+template <>
+struct LdsLayout<float> {
+  __host__ __device__ static constexpr int idx(int i) { return i + (i >> 5); }
+  __host__ __device__ static constexpr int join(int a, int b) { return a + b; }
+  __host__ __device__ static constexpr int row_stride(int n) { return n + (n >> 5) + 1; }
+  __host__ __device__ static constexpr int col_stride(int n) { return n + (n >> 5) + 1; }
+};
+template <>
+struct LdsLayout<double> {
+  __host__ __device__ static constexpr int idx(int i) { return i ^ (((i >> 4) ^ (i >> 5)) & 15); }
+  __host__ __device__ static constexpr int join(int a, int b) { return a ^ b; }
+  __host__ __device__ static constexpr int row_stride(int n) { return n + 8; }
+  __host__ __device__ static constexpr int col_stride(int n) { return n + 4; }
+};
+template <typename T>
+__host__ __device__ constexpr int lds_idx(int i) { return LdsLayout<T>::idx(i); }
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 

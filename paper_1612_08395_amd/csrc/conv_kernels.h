@@ -132,7 +132,7 @@ struct min_waves_of<F, std::void_t<decltype(F::kMinWaves)>> {
 template <typename T, int L, int NTHR, class Pro>
 __global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
                                                   int ny, const cplx<T>* __restrict__ tw) {
-  constexpr int STR = lds_len(L);
+  constexpr int STR = LdsLayout<T>::row_stride(L);
   constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
@@ -149,8 +149,8 @@ __global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro 
     const int n = threadIdx.x + q * NTHR;
     if (PER * NTHR == L || n < L) {
       const cplx<T> z = {va[q], vb[q]};
-      lds[lds_pad(n)] = z;
-      lds[STR + lds_pad(n)] = cmul(z, tw[n]);
+      lds[lds_idx<T>(n)] = z;
+      lds[STR + lds_idx<T>(n)] = cmul(z, tw[n]);
     }
   }
   pro.template commit<NTHR>(ya, yb, hasb, nx, va, vb);
@@ -163,18 +163,18 @@ __global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro 
   const T half = T(0.5);
   for (int k = threadIdx.x; k < L; k += NTHR) {
     if (k == 0) {
-      const cplx<T> z0 = E[lds_pad(0)], zl = E[lds_pad(L / 2)];
+      const cplx<T> z0 = E[lds_idx<T>(0)], zl = E[lds_idx<T>(L / 2)];
       Sa[0] = {z0.x, zl.x};
       if (hasb) Sb[0] = {z0.y, zl.y};
     } else {
       const int kp = k >> 1;
       cplx<T> Z, Zp;
       if ((k & 1) == 0) {
-        Z = E[lds_pad(kp)];
-        Zp = E[lds_pad(L - kp)];
+        Z = E[lds_idx<T>(kp)];
+        Zp = E[lds_idx<T>(L - kp)];
       } else {
-        Z = O[lds_pad(kp)];
-        Zp = O[lds_pad(L - 1 - kp)];
+        Z = O[lds_idx<T>(kp)];
+        Zp = O[lds_idx<T>(L - 1 - kp)];
       }
       Sa[k] = {half * (Z.x + Zp.x), half * (Z.y - Zp.y)};
       if (hasb) Sb[k] = {half * (Z.y + Zp.y), half * (Zp.x - Z.x)};
@@ -237,7 +237,7 @@ __device__ __forceinline__ void col_multiply(cplx<T>* lds, int c0, int lx, const
     const int ky = 2 * kp + (s & 1);
     const int kq = ky <= LY ? ky : 2 * LY - ky;
     const T kv = KT[(size_t)(c0 + c) * kpitch + kq];
-    cplx<T>* a = lds + s * STR + lds_pad(kp);
+    cplx<T>* a = lds + s * STR + lds_idx<T>(kp);
     *a = cscale(*a, kv);
   }
   if (c0 == 0) {
@@ -262,8 +262,8 @@ __device__ __forceinline__ void col_multiply(cplx<T>* lds, int c0, int lx, const
       if (seq == 1 && i0 >= LY / 2) continue;
       const int kq = ky <= LY ? ky : 2 * LY - ky;
       const T a = half * (K0[kq] + K1[kq]), b = half * (K0[kq] - K1[kq]);
-      cplx<T>* p0 = lds + seq * STR + lds_pad(i0);
-      cplx<T>* p1 = lds + seq * STR + lds_pad(i1);
+      cplx<T>* p0 = lds + seq * STR + lds_idx<T>(i0);
+      cplx<T>* p1 = lds + seq * STR + lds_idx<T>(i1);
       const cplx<T> z0 = *p0, z1 = *p1;
       *p0 = {a * z0.x + b * z1.x, a * z0.y - b * z1.y};
       if (i1 != i0) *p1 = {a * z1.x + b * z0.x, a * z1.y - b * z0.y};
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
                                                    const cplx<T>* __restrict__ tw,
                                                    const int* __restrict__ done) {
   if (done && *done) return;
-  constexpr int STR = lds_len(LY);
+  constexpr int STR = LdsLayout<T>::col_stride(LY);
   __shared__ cplx<T> lds[2 * W * STR];
   const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
   using Stage = ColStage<T, LY, W, NTHR>;
@@ -288,8 +288,8 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
     for (int j = 0; j < Stage::CNT; ++j)
       if (Stage::valid(j)) {
         const int c = Stage::col(j), n = Stage::row(j);
-        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
-        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+        lds[(2 * c) * STR + lds_idx<T>(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_idx<T>(n)] = cmul(st.x[j], tw[n]);
       }
   }
   __syncthreads();
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
   for (int j = 0; j < Stage::CNT; ++j) {
     const int c = Stage::col(j), n = Stage::row(j);
     if (Stage::valid(j)) {
-      const cplx<T> e = lds[(2 * c) * STR + lds_pad(n)];
-      const cplx<T> o = lds[(2 * c + 1) * STR + lds_pad(n)];
+      const cplx<T> e = lds[(2 * c) * STR + lds_idx<T>(n)];
+      const cplx<T> o = lds[(2 * c + 1) * STR + lds_idx<T>(n)];
       y[j] = cadd(e, cmulc(o, tw[n]));
     }
   }
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
                                                      const int* __restrict__ done,
                                                      double* __restrict__ part) {
   if (done && *done) return;
-  constexpr int STR = lds_len(LY);
+  constexpr int STR = LdsLayout<T>::col_stride(LY);
   __shared__ cplx<T> lds[2 * W * STR];
   __shared__ double red[64];
   const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
@@ -355,8 +355,8 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
     for (int j = 0; j < Stage::CNT; ++j)
       if (Stage::valid(j)) {
         const int c = Stage::col(j), n = Stage::row(j);
-        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
-        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+        lds[(2 * c) * STR + lds_idx<T>(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_idx<T>(n)] = cmul(st.x[j], tw[n]);
       }
   }
   __syncthreads();
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
     if (c0 + c == 0) continue;
     const int ky = 2 * kp + (s & 1);
     const int kq = ky <= LY ? ky : 2 * LY - ky;
-    e += energy_term(lds[s * STR + lds_pad(kp)], KT[(size_t)(c0 + c) * kpitch + kq]);
+    e += energy_term(lds[s * STR + lds_idx<T>(kp)], KT[(size_t)(c0 + c) * kpitch + kq]);
   }
   if (c0 == 0) {
     // column 0: sequences 0 (even ky) and 1 (odd ky); partner of ky is -ky
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
       const int kpp = s ? LY - 1 - kp : (LY - kp) & (LY - 1);
       const int ky = 2 * kp + s;
       const int kq = ky <= LY ? ky : 2 * LY - ky;
-      e += energy_packed(lds[s * STR + lds_pad(kp)], lds[s * STR + lds_pad(kpp)], KT[kq],
+      e += energy_packed(lds[s * STR + lds_idx<T>(kp)], lds[s * STR + lds_idx<T>(kpp)], KT[kq],
                          KT[(size_t)lx * kpitch + kq]);
     }
   }
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
 template <typename T, int L, int NTHR, class Epi>
 __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
                                                   const cplx<T>* __restrict__ tw, Epi epi_arg) {
-  constexpr int STR = lds_len(L);
+  constexpr int STR = LdsLayout<T>::row_stride(L);
   constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
@@ -422,14 +422,14 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
     // for every load in flight); Bv is finite data of a valid row
     const cplx<T> B = cscale(Bv[j], hasb ? T(1) : T(0));
     if (k == 0) {
-      lds[lds_pad(0)] = {A.x, B.x};        // Z[0]  = A[0]  + i B[0]
-      lds[lds_pad(L / 2)] = {A.y, B.y};    // Z[Lx] = A[Lx] + i B[Lx]
+      lds[lds_idx<T>(0)] = {A.x, B.x};        // Z[0]  = A[0]  + i B[0]
+      lds[lds_idx<T>(L / 2)] = {A.y, B.y};    // Z[Lx] = A[Lx] + i B[Lx]
     } else {
       const cplx<T> Z = {A.x - B.y, A.y + B.x};    // A + i B
       const cplx<T> Zm = {A.x + B.y, B.x - A.y};   // conj(A) + i conj(B) = Z[Mx - k]
       const int km = 2 * L - k;
-      lds[(k & 1) * STR + lds_pad(k >> 1)] = Z;
-      lds[(km & 1) * STR + lds_pad(km >> 1)] = Zm;
+      lds[(k & 1) * STR + lds_idx<T>(k >> 1)] = Z;
+      lds[(km & 1) * STR + lds_idx<T>(km >> 1)] = Zm;
     }
   }
   __syncthreads();
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
   for (int q = 0; q < PER; ++q) {
     const int n = threadIdx.x + q * NTHR;
     cplx<T> z = {T(0), T(0)};
-    if (n < nx) z = cadd(lds[lds_pad(n)], cmulc(lds[STR + lds_pad(n)], tw[n]));
+    if (n < nx) z = cadd(lds[lds_idx<T>(n)], cmulc(lds[STR + lds_idx<T>(n)], tw[n]));
     va[q] = z.x;
     vb[q] = z.y;
   }
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(NTHR) void k_col_spectrum(const cplx<double>* __res
                                                        double* __restrict__ KT64,
                                                        float* __restrict__ KT32, int kpitch,
                                                        double scale) {
-  constexpr int STR = lds_len(LY);
+  constexpr int STR = LdsLayout<double>::col_stride(LY);
   __shared__ cplx<double> lds[2 * W * STR];
   const int c0 = blockIdx.x * W;
   {
@@ -467,8 +467,8 @@ __global__ __launch_bounds__(NTHR) void k_col_spectrum(const cplx<double>* __res
     for (int j = 0; j < Stage::CNT; ++j)
       if (Stage::valid(j)) {
         const int c = Stage::col(j), n = Stage::row(j);
-        lds[(2 * c) * STR + lds_pad(n)] = st.x[j];
-        lds[(2 * c + 1) * STR + lds_pad(n)] = cmul(st.x[j], tw[n]);
+        lds[(2 * c) * STR + lds_idx<double>(n)] = st.x[j];
+        lds[(2 * c + 1) * STR + lds_idx<double>(n)] = cmul(st.x[j], tw[n]);
       }
   }
   __syncthreads();
@@ -476,8 +476,8 @@ __global__ __launch_bounds__(NTHR) void k_col_spectrum(const cplx<double>* __res
   for (int f = threadIdx.x; f < W * (LY + 1); f += NTHR) {
     const int c = f / (LY + 1), ky = f % (LY + 1);
     const int kn = (2 * LY - ky) & (2 * LY - 1);
-    const cplx<double> yk = lds[(2 * c + (ky & 1)) * STR + lds_pad(ky >> 1)];
-    const cplx<double> yn = lds[(2 * c + (kn & 1)) * STR + lds_pad(kn >> 1)];
+    const cplx<double> yk = lds[(2 * c + (ky & 1)) * STR + lds_idx<double>(ky >> 1)];
+    const cplx<double> yn = lds[(2 * c + (kn & 1)) * STR + lds_idx<double>(kn >> 1)];
     const int cg = c0 + c;
     const double v = 2.0 * (yk.x + yn.x) * scale;
     KT64[(size_t)cg * kpitch + ky] = v;

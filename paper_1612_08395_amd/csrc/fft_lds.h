@@ -3,7 +3,7 @@
 //
 // The transform of Eq. 13 is the only place the method needs an FFT; these
 // routines carry it.  A workgroup transforms NSEQ independent sequences of
-// length L that sit in LDS at seq * STRIDE (padded with lds_pad).  Each pass
+// length L that sit in LDS at seq * STRIDE, element i at lds_idx<T>(i).  Each pass
 // reads R points spaced L/R apart into registers, applies the twiddles
 // w^(r k), does an R-point DFT and writes the R results Ns apart (Stockham
 // auto-sort: natural order in and out, one LDS buffer, two barriers a pass).
@@ -160,8 +160,10 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* lds, const cplx<T>* __res
       const int s = f / NB, j = f % NB;
       const int k = j % NS;
       cplx<T>* base = lds + s * STRIDE;
+      // j < NB and r NB share no bits
+      const int pj = lds_idx<T>(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = base[lds_pad(j + r * NB)];
+      for (int r = 0; r < R; ++r) v[b][r] = base[LdsLayout<T>::join(pj, lds_idx<T>(r * NB))];
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -181,8 +183,10 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* lds, const cplx<T>* __res
       const int k = j % NS;
       cplx<T>* base = lds + s * STRIDE;
       const int o = (j - k) * R + k;
+      // k < NS, r NS < R NS and (j - k) R (a multiple of R NS) share no bits
+      const int po = lds_idx<T>(o);
 #pragma unroll
-      for (int r = 0; r < R; ++r) base[lds_pad(o + r * NS)] = v[b][r];
+      for (int r = 0; r < R; ++r) base[LdsLayout<T>::join(po, lds_idx<T>(r * NS))] = v[b][r];
     }
   }
   __syncthreads();

@@ -38,7 +38,7 @@ template <typename T>
 __host__ __device__ constexpr int col_width_lds(int LY) {
   // largest power of two W <= 16 with 2 W padded columns within ~150 KB LDS
   int w = 16;
-  while (w > 1 && 2 * w * lds_len(LY) * (int)sizeof(cplx<T>) > 150 * 1024) w >>= 1;
+  while (w > 1 && 2 * w * LdsLayout<T>::col_stride(LY) * (int)sizeof(cplx<T>) > 150 * 1024) w >>= 1;
   return w;
 }
 
