@@ -692,6 +692,47 @@ __global__ __launch_bounds__(EW_THREADS) void k_cold_start(T* __restrict__ p, co
   }
 }
 
+// First iteration of a warm-started displacement-controlled solve within a
+// sweep over d (same h): the state's g = C K * p + h - d_old belongs to the
+// unchanged p, so the new gap is g + (d_old - d_new) and the iteration's
+// first convolution can be skipped.  One workgroup per row pair writes the
+// partial sums that the update prologue (sum |p|; nothing is updated at
+// iteration 0) and the gap epilogue (sum over Ic of g^2 and of (h - d)^2)
+// would have written.
+template <typename T, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_gap_shift(T* __restrict__ g, const T* __restrict__ hd,
+                                                    const T* __restrict__ p,
+                                                    const uint8_t* __restrict__ mask,
+                                                    double delta, double* __restrict__ part,
+                                                    int nx, int ny) {
+  __shared__ double red[64];
+  const int ya = 2 * blockIdx.x;
+  const int rows = ya + 1 < ny ? 2 : 1;
+  double acc[3] = {0.0, 0.0, 0.0};   // sum |p|, sum_Ic g^2, sum_Ic (h - d)^2
+  for (int r = 0; r < rows; ++r) {
+    const size_t base = (size_t)(ya + r) * nx;
+    for (int n = threadIdx.x; n < nx; n += NTHR) {
+      const size_t i = base + n;
+      const T gv = (T)((double)g[i] + delta);
+      g[i] = gv;
+      acc[0] += fabs((double)p[i]);
+      if (mask[i]) {
+        const double h = (double)hd[i];
+        acc[1] += (double)gv * (double)gv;
+        acc[2] += h * h;
+      }
+    }
+  }
+  block_sum_n<3, NTHR>(acc, red);
+  if (threadIdx.x == 0) {
+    part[kPartUpd + blockIdx.x * 3 + 0] = 0.0;
+    part[kPartUpd + blockIdx.x * 3 + 1] = acc[0];
+    part[kPartUpd + blockIdx.x * 3 + 2] = 0.0;
+    part[kPartGap + blockIdx.x * 2 + 0] = acc[1];
+    part[kPartGap + blockIdx.x * 2 + 1] = acc[2];
+  }
+}
+
 // Zero the direction; fixed-set mode: zero the pressure off the contact set;
 // non-adhesive mode: clip a warm-start pressure to p >= 0.
 template <typename T>

@@ -32,31 +32,42 @@ inline hipError_t mark(const hipEvent_t* ev, int k, hipStream_t s) {
 
 template <typename T, int MODE>
 hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int it,
-                               const hipEvent_t* ev, hipStream_t s) {
+                               const hipEvent_t* ev, hipStream_t s, const double* shift) {
   const int nrp = (g.ny + 1) / 2;
   const int nbc = col_energy_blocks<T>(g);
-  // R2C sweeps: Stockham (their prologues carry most of the work, and the
-  // wave kernels' lower occupancy costs more than their cheaper transform
-  // saves); C2R sweeps: wave kernels at Lx = 2048, except under load
-  // control, whose epilogues do not fit the wave kernel's registers
-  hipError_t e = launch_row_r2c<T, false>(
-      g, K, b.S,
-      [&](auto PERc) {
-        return UpdatePro<T, MODE, decltype(PERc)::value>{b.p,    b.t,    b.g, b.mask, b.sc,
-                                                          b.part, g.nx, nrp, it,     nbc};
-      },
-      s);
-  if (e != hipSuccess || (e = mark(ev, 0, s)) != hipSuccess) return e;
-  if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
-  if ((e = mark(ev, 1, s)) != hipSuccess) return e;
-  e = launch_row_c2r<T, MODE != CG_FORCE>(
-      g, K, b.S,
-      [&](auto PERc) {
-        return GapEpi<T, MODE, decltype(PERc)::value>{b.g,    b.hd, b.p, b.mask, b.sc,
-                                                       b.part, g.nx, nrp, it};
-      },
-      s);
-  if (e != hipSuccess || (e = mark(ev, 2, s)) != hipSuccess) return e;
+  hipError_t e;
+  if (shift) {
+    // iteration 0 after a solve of the same p at another d: the gap by a
+    // shift instead of the first convolution (the three events follow it)
+    hipLaunchKernelGGL((k_gap_shift<T, 256>), dim3(nrp), dim3(256), 0, s, b.g, b.hd, b.p, b.mask,
+                       *shift, b.part, g.nx, g.ny);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int k = 0; k < 3; ++k)
+      if ((e = mark(ev, k, s)) != hipSuccess) return e;
+  } else {
+    // R2C sweeps: Stockham (their prologues carry most of the work, and the
+    // wave kernels' lower occupancy costs more than their cheaper transform
+    // saves); C2R sweeps: wave kernels at Lx = 2048, except under load
+    // control, whose epilogues do not fit the wave kernel's registers
+    e = launch_row_r2c<T, false>(
+        g, K, b.S,
+        [&](auto PERc) {
+          return UpdatePro<T, MODE, decltype(PERc)::value>{b.p,    b.t,    b.g, b.mask, b.sc,
+                                                            b.part, g.nx, nrp, it,     nbc};
+        },
+        s);
+    if (e != hipSuccess || (e = mark(ev, 0, s)) != hipSuccess) return e;
+    if ((e = launch_col<T>(g, K, b.S, &b.sc->done, s)) != hipSuccess) return e;
+    if ((e = mark(ev, 1, s)) != hipSuccess) return e;
+    e = launch_row_c2r<T, MODE != CG_FORCE>(
+        g, K, b.S,
+        [&](auto PERc) {
+          return GapEpi<T, MODE, decltype(PERc)::value>{b.g,    b.hd, b.p, b.mask, b.sc,
+                                                         b.part, g.nx, nrp, it};
+        },
+        s);
+    if (e != hipSuccess || (e = mark(ev, 2, s)) != hipSuccess) return e;
+  }
   e = launch_row_r2c<T, false>(
       g, K, b.S,
       [&](auto PERc) {
@@ -88,18 +99,23 @@ hipError_t launch_cg_iteration(const Geom& g, const SpecView<T>& K, const CgBufs
 }
 
 // Queue iterations it0 .. it0 + n - 1.  ev (optional): 6 n + 1 events, the
-// first recorded before the first launch, then six per iteration.
+// first recorded before the first launch, then six per iteration.  shift
+// (displacement control only, it0 = 0): iteration 0 takes its gap from the
+// state's g shifted by *shift (k_gap_shift).
 template <typename T>
 hipError_t launch_cg_iterations(const Geom& g, const SpecView<T>& K, const CgBufs<T>& b, int mode,
-                                int it0, int n, const hipEvent_t* ev, hipStream_t s) {
+                                int it0, int n, const hipEvent_t* ev, hipStream_t s,
+                                const double* shift) {
+  if (shift && (mode != CG_DISP || it0 != 0)) return hipErrorInvalidValue;
   hipError_t e = mark(ev, 0, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < n; ++i) {
     const hipEvent_t* evi = ev ? ev + 1 + 6 * i : nullptr;
+    const double* sh = i == 0 ? shift : nullptr;
     switch (mode) {
-      case CG_DISP: e = launch_cg_iteration<T, CG_DISP>(g, K, b, it0 + i, evi, s); break;
-      case CG_FIXED: e = launch_cg_iteration<T, CG_FIXED>(g, K, b, it0 + i, evi, s); break;
-      case CG_FORCE: e = launch_cg_iteration<T, CG_FORCE>(g, K, b, it0 + i, evi, s); break;
+      case CG_DISP: e = launch_cg_iteration<T, CG_DISP>(g, K, b, it0 + i, evi, s, sh); break;
+      case CG_FIXED: e = launch_cg_iteration<T, CG_FIXED>(g, K, b, it0 + i, evi, s, nullptr); break;
+      case CG_FORCE: e = launch_cg_iteration<T, CG_FORCE>(g, K, b, it0 + i, evi, s, nullptr); break;
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -181,7 +197,8 @@ hipError_t launch_u_from_gap(const T* g, const double* h, double d, double* u, s
 
 #define BEM_INSTANTIATE_CG(T)                                                                    \
   template hipError_t launch_cg_iterations<T>(const Geom&, const SpecView<T>&, const CgBufs<T>&, \
-                                              int, int, int, const hipEvent_t*, hipStream_t);    \
+                                              int, int, int, const hipEvent_t*, hipStream_t,     \
+                                              const double*);                                    \
   template hipError_t launch_fill<T>(T*, double, size_t, hipStream_t);                           \
   template hipError_t launch_min_h<T>(const double*, size_t, CgScal*, hipStream_t);              \
   template hipError_t launch_make_hd<T>(const double*, double, T*, size_t, hipStream_t);         \

@@ -18,6 +18,7 @@ struct Seg {
   int it0, n;     // iterations it0 .. it0 + n - 1
   int final_it;   // iteration at which the solver stopped; INT_MAX: not in
                   // this chunk; INT_MIN: chunk never completed (skip it)
+  bool shifted;   // iteration it0 began with a gap shift (launches 0-2 absent)
 };
 
 struct Clock {
@@ -49,10 +50,15 @@ const hipEvent_t* clock_chunk(int it0, int n) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     c.pool.push_back(e);
   }
-  c.segs.push_back({c.used, it0, n, INT_MIN});
+  c.segs.push_back({c.used, it0, n, INT_MIN, false});
   const hipEvent_t* ev = c.pool.data() + c.used;
   c.used = need;
   return ev;
+}
+
+void clock_chunk_shifted() {
+  Clock& c = tl_clock;
+  if (c.on && !c.segs.empty()) c.segs.back().shifted = true;
 }
 
 void clock_chunk_done(bool done, int final_it) {
@@ -95,6 +101,9 @@ int bem_clock_stop(bem_clock_t* out) {
         const hipError_t e = hipEventElapsedTime(&ms, c.pool[sg.base + 6 * (size_t)i + k],
                                                  c.pool[sg.base + 6 * (size_t)i + k + 1]);
         if (e != hipSuccess) return hip_fail(e, "bem_clock_stop: event timing");
+        // after a gap shift the first three intervals of iteration it0 hold only
+        // the shift kernel, which none of the six launch slots describes
+        if (sg.shifted && i == 0 && k <= 2) continue;
         // at the stopping iteration the direction kernel only takes the decision
         const bool worked = j < sg.final_it || (j == sg.final_it && k <= 2);
         if (worked) {

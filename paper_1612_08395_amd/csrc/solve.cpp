@@ -38,6 +38,10 @@ struct bem_state_s {
   CgScal* sc = nullptr;
   CgScal* sc_host = nullptr;  // pinned
   bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
+  // g = C K * p + h - g_d for the current p (set by a displacement-controlled
+  // solve; a sweep's next step at another d starts from it, same h)
+  bool g_valid = false;
+  double g_d = 0.0;
   long long device_bytes = 0;
   int last_iters[3] = {0, 0, 0};  // iterations of the previous CG solve, per mode
 };
@@ -123,9 +127,11 @@ int status_code(int st) {
 
 // Run one CG solve to convergence on the device.  Returns the status code;
 // *iters receives the iterations of this solve.
+// shift (displacement control): iteration 0 takes its gap from the state's g
+// shifted by *shift instead of the first convolution.
 template <typename T>
 int run_cg(bem_state_s* st, int mode, const SolveCfg& cfg, int* iters, double* resid,
-           hipStream_t s) {
+           hipStream_t s, const double* shift = nullptr) {
   const bool fixed_set = mode == CG_FIXED;
   CgScal* h = st->sc_host;
   std::memset(h, 0, sizeof(CgScal));
@@ -148,7 +154,9 @@ int run_cg(bem_state_s* st, int mode, const SolveCfg& cfg, int* iters, double* r
   int it = 0;
   for (;;) {
     const hipEvent_t* ev = clock_chunk(it, chunk);
-    if ((e = launch_cg_iterations<T>(g, K, b, mode, it, chunk, ev, s)) != hipSuccess)
+    const double* sh = it == 0 ? shift : nullptr;
+    if (sh) clock_chunk_shifted();
+    if ((e = launch_cg_iterations<T>(g, K, b, mode, it, chunk, ev, s, sh)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
     it += chunk;
     if ((e = hipMemcpyAsync(h, st->sc, sizeof(CgScal), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -200,9 +208,13 @@ int apply_import(bem_state_s* st, hipStream_t s) {
 template <typename T>
 int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool adhesive,
                 double pcrit, double* p_out, unsigned char* c_out, double* u_out, bool outs_host,
-                bem_result* res, hipStream_t s) {
+                bem_result* res, hipStream_t s, bool sweep_step) {
   bem_influence_s* K = st->K;
   const size_t n = st->n;
+  // the previous solve's g may seed this one (sweep steps only: same h)
+  const bool g_ok = sweep_step && st->g_valid && !st->pending_import;
+  const double g_d = st->g_d;
+  st->g_valid = false;
   int rc = apply_import<T>(st, s);
   if (rc) return rc;
   SolveCfg cfg;
@@ -218,18 +230,23 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
   auto non_adhesive = [&](double d) -> int {
     hipError_t ee = launch_make_hd<T>(h_dev, d, (T*)st->hd, n, s);
     if (ee != hipSuccess) return hip_fail(ee, "gap profile");
+    const bool warm = st->has_p;
     if (!st->has_p) {
       ee = launch_cold_start<T>((T*)st->p, (const T*)st->hd, inv_ck00, n, s);
       if (ee != hipSuccess) return hip_fail(ee, "cold start");
       st->has_p = true;
     }
-    int r = run_cg<T>(st, CG_DISP, cfg, &it, &resid, s);
+    // g = C K * p + h - g_d  ->  g + (g_d - d) = C K * p + h - d
+    const double shift = g_d - d;
+    int r = run_cg<T>(st, CG_DISP, cfg, &it, &resid, s, (g_ok && warm) ? &shift : nullptr);
     if (r < 0) return r;
     status = worse(status, r);
     iters_total += it;
     int f = finalize<T>(st, CG_DISP, s);
     if (f) return f;
     st->has_mask = true;
+    st->g_valid = true;
+    st->g_d = d;
     return BEM_OK;
   };
 
@@ -278,6 +295,7 @@ int solve_typed(bem_state_s* st, const double* h_dev, const bem_params& P, bool 
     }
     if ((e = launch_make_hd<T>(h_dev, P.d, (T*)st->hd, n, s)) != hipSuccess)
       return hip_fail(e, "gap profile");
+    st->g_valid = false;   // the fixed-set solves change p
     for (;;) {
       int r = run_cg<T>(st, CG_FIXED, cfg, &it, &resid, s);
       if (r < 0) return r;
@@ -418,7 +436,7 @@ int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, 
 
 int solve_common(bem_influence_t K, const double* h_dev, const bem_params* prm, bem_state_t state,
                  double* p_out, unsigned char* c_out, double* u_out, bool outs_host,
-                 bem_result* res, hipStream_t s) {
+                 bem_result* res, hipStream_t s, bool sweep_step = false) {
   bool adhesive;
   double pcrit;
   int rc = check_params(K, prm, &adhesive, &pcrit);
@@ -437,9 +455,9 @@ int solve_common(bem_influence_t K, const double* h_dev, const bem_params* prm, 
   if (rc == BEM_OK) {
     rc = prm->precision == BEM_FP64
              ? solve_typed<double>(state, h_dev, *prm, adhesive, pcrit, p_out, c_out, u_out,
-                                   outs_host, res, s)
+                                   outs_host, res, s, sweep_step)
              : solve_typed<float>(state, h_dev, *prm, adhesive, pcrit, p_out, c_out, u_out,
-                                  outs_host, res, s);
+                                  outs_host, res, s, sweep_step);
   }
   if (tmp) bem_state_free(tmp);
   return rc;
@@ -454,6 +472,7 @@ int sweep_steps(bem_influence_t K, const double* h_dev, const bem_params* prm,
                 bem_result* res, hipStream_t s) {
   int worst = BEM_OK;
   const bool adhesive = prm->gamma > 0.0 || prm->p_crit > 0.0;
+  state->g_valid = false;   // g may belong to another gap profile
   for (int i = first; i < n_steps; i += stride) {
     bem_params P = *prm;
     if (prm->control == BEM_CTRL_FORCE)
@@ -465,7 +484,8 @@ int sweep_steps(bem_influence_t K, const double* h_dev, const bem_params* prm,
       P.gamma = 0.0;
       P.p_crit = 0.0;
     }
-    const int r = solve_common(K, h_dev, &P, state, nullptr, nullptr, nullptr, true, &res[i], s);
+    const int r =
+        solve_common(K, h_dev, &P, state, nullptr, nullptr, nullptr, true, &res[i], s, true);
     if (r < 0) return r;
     worst = worse(worst, r);
   }
@@ -484,6 +504,7 @@ int state_copy(bem_state_s* dst, const bem_state_s* src, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "state copy");
   dst->has_p = src->has_p;
   dst->has_mask = src->has_mask;
+  dst->g_valid = false;   // g is not copied
   dst->pending_import = dst->import_mask = false;
   std::copy(src->last_iters, src->last_iters + 3, dst->last_iters);
   return BEM_OK;
@@ -555,7 +576,7 @@ int bem_state_free(bem_state_t st) {
 int bem_state_reset(bem_state_t st) {
   clear_error();
   if (!st) return set_error(BEM_EINVAL, "bem_state_reset: NULL state");
-  st->has_p = st->has_mask = st->pending_import = st->import_mask = false;
+  st->has_p = st->has_mask = st->pending_import = st->import_mask = st->g_valid = false;
   st->last_iters[0] = st->last_iters[1] = st->last_iters[2] = 0;
   return BEM_OK;
 }

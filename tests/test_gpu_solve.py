@@ -236,6 +236,36 @@ def test_sweep_dev_concurrent_chains(chains):
     K.free()
 
 
+def test_sweep_state_from_another_profile():
+    # Sweep steps after the first start from the previous step's gap shifted
+    # to the new depth.  A state whose last solve was on another gap profile
+    # must not hand its gap to a sweep: every step against the oracle, in
+    # both precisions, then a second sweep on the same state.
+    bem = _bem()
+    announce("sweep-other-profile")
+    n, L, k, nu = 80, 1.0, 0.2, 0.3
+    dx, Kq, C, conv = _oracle(n, L, k, nu)
+    h = inputs.parabolic(n, L, 1.0)
+    h2 = inputs.fractal_gap(n, L, 0.7, 4 * 2 * math.pi / L, 20 * 2 * math.pi / L, 1e-3 * L, 5)
+    ds = [0.002, 0.004, 0.006, 0.008]
+    refs = [so.solve_nonadhesive(Kq, C, h, d, tol=1e-12, conv=conv) for d in ds]
+    K = bem.bem_influence(n, n, dx, k, nu)
+    for prec, tol in ((bem.BEM_FP64, FP64_TOL), (bem.BEM_MIXED, MIXED_TOL)):
+        st = bem.bem_state_create(K)
+        d2 = float(np.quantile(h2, 0.1))
+        bem.bem_solve(K, h2, bem.bem_params_init(d=d2, precision=prec), state=st)
+        for _ in range(2):
+            rc, sw = bem.bem_sweep(K, h, bem.bem_params_init(precision=prec), ds, state=st)
+            for r, ref in zip(sw, refs):
+                assert r.status in (0, bem.BEM_EFLOOR)
+                assert r.F == pytest.approx(so.force(ref.p, dx, dx), rel=max(tol, 1e-10))
+                assert _count_close(r.n_contact, ref.contact.sum())
+        p_s, _ = bem.bem_state_get(st)
+        assert rel_l2(p_s, refs[-1].p) <= tol
+        st.free()
+    K.free()
+
+
 def test_sweep_dev_argument_errors():
     import torch
     bem = _bem()
