@@ -224,6 +224,9 @@ int bem_solve_dev(bem_influence_t K, const double* h, const bem_params* prm, bem
  * warm-started from step to step on the device (Section 3.1).  With
  * adhesion, a step whose d is below the previous step's is a pull-off step
  * (adhesive solve); every other step is a non-adhesive (loading) solve.
+ * A displacement-controlled step that follows another on the same state
+ * takes its first gap from the previous step's (h is the same, only d moves)
+ * instead of a convolution; results are those of separate warm-started solves.
  * h: host ny x nx FP64.  res: n_steps results.  state: NULL = temporary.
  */
 int bem_sweep(bem_influence_t K, const double* h, const bem_params* prm, const double* d_list,
