@@ -266,6 +266,36 @@ def test_sweep_state_from_another_profile():
     K.free()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sweep_matches_separate_warm_solves(prec):
+    # A sweep step takes its first gap from the previous step's (a shift by
+    # the change of d); separate bem_solve calls on a warm state recompute it
+    # by convolution.  Same pressures (to rounding) and iteration counts.
+    bem = _bem()
+    announce("sweep-vs-solves", prec)
+    precision = bem.BEM_FP64 if prec == "fp64" else bem.BEM_MIXED
+    n, L, k, nu = 128, 1.0, 0.3, 0.3
+    dx = L / n
+    h = inputs.fractal_gap(n, L, 0.7, 4 * 2 * math.pi / L, 32 * 2 * math.pi / L, 1e-3 * L, 41)
+    ds = [float(np.quantile(h, q)) for q in (0.02, 0.04, 0.06, 0.08, 0.10)]
+    K = bem.bem_influence(n, n, dx, k, nu)
+    st = bem.bem_state_create(K)
+    rc, sw = bem.bem_sweep(K, h, bem.bem_params_init(precision=precision), ds, state=st)
+    p_sweep, _ = bem.bem_state_get(st)
+    st2 = bem.bem_state_create(K)
+    for d, r in zip(ds, sw):
+        _, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, precision=precision),
+                                        state=st2)
+        assert abs(res.iters - r.iters) <= 1
+        assert res.n_contact == r.n_contact if prec == "fp64" else _count_close(res.n_contact,
+                                                                                r.n_contact)
+        assert res.F == pytest.approx(r.F, rel=1e-12 if prec == "fp64" else 1e-6)
+    assert rel_l2(p, p_sweep) <= (1e-12 if prec == "fp64" else 1e-6)
+    st.free()
+    st2.free()
+    K.free()
+
+
 def test_sweep_dev_argument_errors():
     import torch
     bem = _bem()
