@@ -47,8 +47,9 @@ long long state_partial_bytes();
 // that chunk once the host has synchronised.
 const hipEvent_t* clock_chunk(int it0, int n);
 void clock_chunk_done(bool done, int final_it);
-// the chunk just opened starts with a gap shift: its iteration 0 has no
-// update, first-convolution or gap launches (their events are not timed)
+// the chunk just opened (clock_chunk returned events for it) starts with a
+// gap shift: its iteration 0 has no update, first-convolution or gap launches
+// (their events are not timed)
 void clock_chunk_shifted();
 double alpha_kn(double k, double nu);
 bool is_finite(double v);

@@ -155,7 +155,7 @@ int run_cg(bem_state_s* st, int mode, const SolveCfg& cfg, int* iters, double* r
   for (;;) {
     const hipEvent_t* ev = clock_chunk(it, chunk);
     const double* sh = it == 0 ? shift : nullptr;
-    if (sh) clock_chunk_shifted();
+    if (sh && ev) clock_chunk_shifted();   // ev: this chunk has a clock segment
     if ((e = launch_cg_iterations<T>(g, K, b, mode, it, chunk, ev, s, sh)) != hipSuccess)
       return hip_fail(e, "CG iteration launch");
     it += chunk;
