@@ -334,6 +334,9 @@ int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void*
  *   the spectral inner product sum t (C K * t)  (force control: full column
  *   sweep),  5 row C2R + dot products (force control only; otherwise no
  *   launch and a zero-length interval).
+ * In a sweep, iteration 0 of a step that starts from the previous step's
+ * gap has no kinds 0-2 (one gap-shift launch instead); those intervals are
+ * left out of the totals.
  * After bem_clock_start, every bem_solve / bem_solve_dev / bem_sweep made BY
  * THE CALLING THREAD records a HIP event on its solver stream before the
  * first launch of each queued chunk and after every launch; no extra host
