@@ -181,7 +181,9 @@ def roofline(bem, K, clock, torch):
             "loop_us_per_launch": loop,
             "column_energy": {"ms_per_launch": round(e_ms, 5), "algorithmic_bytes_per_launch":
                               e_bytes, "GBps": round(e_bytes / (e_ms * 1e-3) / 1e9, 1)},
-            "loop_us_per_iteration": round(sum(clock.ms) / clock.iterations * 1e3, 2),
+            "loop_us_per_iteration": round(clock.loop_ms() / clock.iterations * 1e3, 2),
+            "gap_shift_launches": clock.shifts,
+            "gap_shift_us_per_launch": round(clock.shift_ms / max(1, clock.shifts) * 1e3, 2),
             "skipped_launches": clock.skipped,
             "skipped_us_total": round(clock.skipped_ms * 1e3, 1)}
 
@@ -315,13 +317,72 @@ def big_grid(bem, torch, depths_n=5):
     return {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395,
             "depths": depths_n, "d_max": dq, "solves_per_s": round(depths_n / t, 3),
             "iters_per_solve": round(iters / depths_n, 2),
-            "loop_us_per_iteration": round(sum(clk.ms) / clk.iterations * 1e3, 2),
+            "loop_us_per_iteration": round(clk.loop_ms() / clk.iterations * 1e3, 2),
             "loop_GBps_algorithmic": round(sum(loop_bytes(r["n_contact"] / (n * n)) * n * n
                                                * r["iters"] for r in res) / t / 1e9, 1),
             "column_us_per_launch": round(col_ms * 1e3, 2),
             "column_GBps_algorithmic": round(col_bytes / (col_ms * 1e-3) / 1e9, 1),
             "contact_area_final": res[-1]["n_contact"] / float(n * n),
             "mixed_vs_fp64_last_depth": acc}
+
+
+# Adhesive leg of the 4096^2 workload: work of adhesion 1e-4 E0 L (the third
+# of the four values {1, 3, 10, 30} 1e-5 the crop tests sweep), 10 loading
+# depths up to D10_4096, then 10 pull-off steps down to -D10_4096 / 4.
+GAMMA_4096 = 1e-4
+
+
+def adhesive_4096(bem, torch, n_load=10, n_unload=10):
+    """Load-unload hysteresis of the 4096^2 rough surface with adhesion
+    (Section 3.1): loading steps are non-adhesive solves, each pull-off step
+    an adhesive solve with detach rounds, all warm-started on one state.  Run
+    step by step in MIXED and in FP64; per step the force, contact count,
+    iterations and detach rounds of both, and the MIXED-vs-FP64 pressure
+    difference."""
+    n, h_dev, K = big_grid_setup(bem, torch)
+    dq = D10_4096
+    depths = [dq * s / n_load for s in range(1, n_load + 1)]
+    depths += [dq * (1.0 - s / (0.8 * n_unload)) for s in range(1, n_unload + 1)]
+    out = {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395, "gamma": GAMMA_4096,
+           "p_crit": bem.bem_p_crit(-0.3, 0.25, GAMMA_4096, L / n),
+           "depths": [float(f"{d:.6e}") for d in depths]}
+    runs = {}
+    for prec, name in ((bem.BEM_MIXED, "mixed"), (bem.BEM_FP64, "fp64")):
+        st = bem.bem_state_create(K)
+        ps, rs = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, d in enumerate(depths):
+            unload = i >= n_load
+            prm = bem.bem_params_init(d=d, precision=prec, gamma=GAMMA_4096 if unload else 0.0)
+            p = torch.empty_like(h_dev)
+            _, r = bem.bem_solve_dev(K, h_dev, prm, state=st, p_out=p)
+            ps.append(p)
+            rs.append(r.as_dict())
+        torch.cuda.synchronize()
+        runs[name] = (time.perf_counter() - t0, ps, rs)
+        st.free()
+    t32, p32, r32 = runs["mixed"]
+    t64, p64, r64 = runs["fp64"]
+    out["mixed_s"] = round(t32, 2)
+    out["fp64_s"] = round(t64, 2)
+    steps = []
+    for i in range(len(depths)):
+        a, b = p32[i], p64[i]
+        nb = float(torch.linalg.norm(b))
+        steps.append({
+            "d": float(f"{depths[i]:.5e}"), "phase": "load" if i < n_load else "unload",
+            "F_mixed": float(f"{r32[i]['F']:.6e}"), "F_fp64": float(f"{r64[i]['F']:.6e}"),
+            "contact_mixed": r32[i]["n_contact"], "contact_fp64": r64[i]["n_contact"],
+            "rel_l2_pressure": float(f"{float(torch.linalg.norm(a - b)) / nb:.3e}") if nb > 0
+            else 0.0,
+            "iters_mixed": r32[i]["iters"], "iters_fp64": r64[i]["iters"],
+            "rounds_mixed": r32[i]["detach_rounds"], "rounds_fp64": r64[i]["detach_rounds"],
+            "status_mixed": r32[i]["status"], "status_fp64": r64[i]["status"]})
+    out["steps"] = steps
+    del p32, p64
+    K.free()
+    return out
 
 
 def oracle_units(cores, Kq):
@@ -417,6 +478,10 @@ def main():
     ap.add_argument("--find-d10-4096", action="store_true")
     ap.add_argument("--no-big-grid", action="store_true",
                     help="skip the 4096^2 (HBM-resident) mixed sweep")
+    ap.add_argument("--no-adhesive-4096", action="store_true",
+                    help="skip the 4096^2 adhesive load-unload leg (MIXED and FP64 per step)")
+    ap.add_argument("--only-adhesive-4096", action="store_true",
+                    help="run only the 4096^2 adhesive load-unload leg and print its JSON")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch each convolution sweep kernel a few times (FP32 and FP64) "
                          "and a 1 GiB device copy, for hardware-counter runs")
@@ -435,6 +500,9 @@ def main():
         return profile_kernels(bem, torch)
     if args.find_d10_4096:
         print(json.dumps({"d10_4096": find_d10_4096(bem, torch)}), flush=True)
+        return 0
+    if args.only_adhesive_4096:
+        print(json.dumps({"adhesive_4096": adhesive_4096(bem, torch)}), flush=True)
         return 0
     log("[bench] building workload")
     h = workload()
@@ -533,6 +601,9 @@ def main():
     if not args.no_big_grid:
         log("[bench] 4096^2 sweep")
         leg("hbm_resident_4096", lambda: big_grid(bem, torch))
+    if not args.no_adhesive_4096:
+        log("[bench] 4096^2 adhesive load-unload")
+        leg("adhesive_4096", lambda: adhesive_4096(bem, torch))
     if args.serving_requests > 0:
         log("[bench] serving")
         leg("serving", lambda: serving(args.serving_requests, args.serving_slots, bem))

@@ -327,7 +327,8 @@ int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void*
 
 /*
  * Solver clock -- measurement hook for the conjugate-gradient loop of the
- * contact solve (Section 2.2, Polonsky-Keer iteration).  Each iteration is
+ * contact solve (the constrained CG method of Section 2.1, which the paper
+ * cites for its inverse problem after Eqs. 12-13).  Each iteration is
  * reported as six launch kinds:
  *   0 pressure update + row R2C,  1 column sweep,  2 row C2R + gap,
  *   3 direction + row R2C,        4 column transform of the direction with
@@ -335,8 +336,8 @@ int bem_kernel_time(bem_influence_t K, int precision, int which, int reps, void*
  *   sweep),  5 row C2R + dot products (force control only; otherwise no
  *   launch and a zero-length interval).
  * In a sweep, iteration 0 of a step that starts from the previous step's
- * gap has no kinds 0-2 (one gap-shift launch instead); those intervals are
- * left out of the totals.
+ * gap has no kinds 0-2 but one gap-shift launch instead, reported as
+ * `shifts` / `shift_ms` (it belongs to the iteration count).
  * After bem_clock_start, every bem_solve / bem_solve_dev / bem_sweep made BY
  * THE CALLING THREAD records a HIP event on its solver stream before the
  * first launch of each queued chunk and after every launch; no extra host
@@ -355,6 +356,8 @@ typedef struct {
   double ms[6];            /* their summed durations (ms) */
   long long skipped;       /* launches queued past convergence */
   double skipped_ms;       /* their summed durations (ms) */
+  long long shifts;        /* gap-shift launches (first iteration of a sweep step) */
+  double shift_ms;         /* their summed durations (ms) */
 } bem_clock_t;
 int bem_clock_start(void);
 int bem_clock_stop(bem_clock_t* out);

@@ -348,13 +348,19 @@ class Clock(ctypes.Structure):
     update+R2C, column, C2R+gap, direction+R2C, column, C2R+dots."""
     _fields_ = [("iterations", ctypes.c_longlong), ("launches", ctypes.c_longlong * 6),
                 ("ms", _c_double * 6), ("skipped", ctypes.c_longlong),
-                ("skipped_ms", _c_double)]
+                ("skipped_ms", _c_double), ("shifts", ctypes.c_longlong),
+                ("shift_ms", _c_double)]
 
     KINDS = ("update_r2c", "column", "gap_c2r", "direction_r2c", "column", "dots_c2r")
 
     def as_dict(self):
         return {"iterations": self.iterations, "launches": list(self.launches),
-                "ms": list(self.ms), "skipped": self.skipped, "skipped_ms": self.skipped_ms}
+                "ms": list(self.ms), "skipped": self.skipped, "skipped_ms": self.skipped_ms,
+                "shifts": self.shifts, "shift_ms": self.shift_ms}
+
+    def loop_ms(self):
+        """Device time of the iterations worked on, gap shifts included."""
+        return sum(self.ms) + self.shift_ms
 
 
 _f_clock_start = _sig("bem_clock_start", _c_int, [])

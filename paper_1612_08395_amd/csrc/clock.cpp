@@ -101,9 +101,15 @@ int bem_clock_stop(bem_clock_t* out) {
         const hipError_t e = hipEventElapsedTime(&ms, c.pool[sg.base + 6 * (size_t)i + k],
                                                  c.pool[sg.base + 6 * (size_t)i + k + 1]);
         if (e != hipSuccess) return hip_fail(e, "bem_clock_stop: event timing");
-        // after a gap shift the first three intervals of iteration it0 hold only
-        // the shift kernel, which none of the six launch slots describes
-        if (sg.shifted && i == 0 && k <= 2) continue;
+        // after a gap shift the first interval of iteration it0 is the shift
+        // kernel (reported on its own) and the next two are empty
+        if (sg.shifted && i == 0 && k <= 2) {
+          if (k == 0) {
+            ++r.shifts;
+            r.shift_ms += ms;
+          }
+          continue;
+        }
         // at the stopping iteration the direction kernel only takes the decision
         const bool worked = j < sg.final_it || (j == sg.final_it && k <= 2);
         if (worked) {

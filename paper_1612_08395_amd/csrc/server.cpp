@@ -42,7 +42,10 @@ using Key = std::tuple<int, int, double, double, double, double, double, double>
 struct Entry {
   Key key;
   bem_influence_t K = nullptr;
-  std::vector<bem_state_t> free_states;
+  // pooled states per precision (index BEM_FP64 / BEM_MIXED): a state's
+  // typed buffers are sized for the precision of the solve that created it,
+  // so it is only ever lent to requests of that precision
+  std::vector<bem_state_t> free_states[2];
   int in_use = 0;
   long long bytes = 0;  // reserved: influence + pooled / lent states
   bool building = false;
@@ -91,8 +94,10 @@ struct bem_server_s {
 namespace {
 
 void free_entry(Entry* e) {
-  for (bem_state_t s : e->free_states) bem_state_free(s);
-  e->free_states.clear();
+  for (auto& pool : e->free_states) {
+    for (bem_state_t s : pool) bem_state_free(s);
+    pool.clear();
+  }
   if (e->K) bem_influence_free(e->K);
   e->K = nullptr;
 }
@@ -104,11 +109,12 @@ void free_entry(Entry* e) {
 Entry* admit(bem_server_s* S, Req* r) {
   const bem_request& q = r->r;
   Key key{q.nx, q.ny, q.dx, q.dy, q.k, q.nu, q.E0, q.c0};
+  const int prec = q.prm.precision;
   auto it = S->cache.find(key);
   Entry* e = it == S->cache.end() ? nullptr : it->second;
   long long need = 0;
   if (!e) need += r->need_infl;
-  if (!e || e->free_states.empty()) need += r->need_state;
+  if (!e || e->free_states[prec].empty()) need += r->need_state;
   while (S->used + need > S->budget) {
     // evict the least recently used idle entry other than this one
     Entry* victim = nullptr;
@@ -136,12 +142,12 @@ Entry* admit(bem_server_s* S, Req* r) {
   } else {
     S->cache_hits++;
   }
-  if (e->free_states.empty()) {
+  if (e->free_states[prec].empty()) {
     e->bytes += r->need_state;
     S->used += r->need_state;
   } else {
-    r->lent = e->free_states.back();
-    e->free_states.pop_back();
+    r->lent = e->free_states[prec].back();
+    e->free_states[prec].pop_back();
   }
   e->in_use++;
   e->last_use = ++S->tick;
@@ -197,13 +203,13 @@ void worker(bem_server_s* S, int slot) {
     }
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (state) e->free_states.push_back(state);
+      if (state) e->free_states[r->r.prm.precision].push_back(state);
       e->in_use--;
       e->last_use = ++S->tick;
       if (!e->K && e->in_use == 0) {  // failed build: drop the entry once unused
         S->cache.erase(e->key);
         S->used -= e->bytes;
-        for (bem_state_t s2 : e->free_states) bem_state_free(s2);
+        free_entry(e);
         delete e;
       }
       r->rc = rc;
@@ -288,6 +294,8 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
   const bem_request& q = *req;
   if (q.nx < 1 || q.ny < 1 || q.nx > BEM_MAX_N || q.ny > BEM_MAX_N)
     return set_error(BEM_EINVAL, "bem_server_submit: grid size");
+  if (q.prm.precision != BEM_FP64 && q.prm.precision != BEM_MIXED)
+    return set_error(BEM_EINVAL, "bem_server_submit: unknown precision %d", q.prm.precision);
   auto* r = new Req();
   r->r = q;
   r->h.assign(q.h, q.h + (size_t)q.nx * q.ny);

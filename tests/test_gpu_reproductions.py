@@ -1,8 +1,10 @@
 """Section 3.2 and 2.2 examples reproduced on the GPU against the closed forms
 (the figure data itself is not published): flat-punch pull-off (Eqs. 25, 26,
 Fig. 6), square punch in four orientations (Fig. 10), the Hertz-type
-k-sweep at 512^2 (Eqs. 15, 16, Fig. 3) and mesh independence of the
-adhesive pull-off (256^2 vs 1024^2, Fig. 7)."""
+k-sweep at 512^2 (Eqs. 15, 16, Fig. 3), mesh independence of the
+adhesive pull-off (256^2 vs 1024^2, Fig. 7), its independence of R / c0
+(Fig. 8a), and Table 1 refitted from BEM pull-offs at every other tabulated k
+(Section 3.1, Fig. 5)."""
 import math
 
 import numpy as np
@@ -128,35 +130,140 @@ def test_mesh_independence_of_pulloff():
     assert Fmin[256] == pytest.approx(Fmin[1024], rel=0.02)
 
 
-@pytest.mark.parametrize("k,L,aF,dj", [(-0.5, 0.6, 0.116, -0.0198), (0.5, 1.2, 0.352, -0.0626)])
-def test_c1_calibration_reproduces_table1(k, L, aF, dj):
+def _jkr_points(k, nu, gam, R, c0=1.0):
+    """Pull-off radius a_F (force minimum) and jump-off depth d_j (indentation
+    minimum) of the JKR-type closed form, which set up the sweeps below."""
+    from scipy import optimize
+    opt = {"xatol": 1e-12}
+    aF = optimize.minimize_scalar(lambda a: an.jkr_curve(k, nu, gam, R, a, 1.0, c0)[1],
+                                  bounds=(1e-6, 10.0), method="bounded", options=opt).x
+    aj = optimize.minimize_scalar(lambda a: an.jkr_curve(k, nu, gam, R, a, 1.0, c0)[0],
+                                  bounds=(1e-6, 10.0), method="bounded", options=opt).x
+    return aF, an.jkr_curve(k, nu, gam, R, aj, 1.0, c0)[0]
+
+
+def _pulloff_sweep(bem, K, h, k, R, aF, dj, prm):
+    """Preload to (1.5 a_F)^2 / ((1+k) R), then 100 pull-off steps of
+    (d0 - d_j) / 95; returns the smallest force and the step results."""
+    d0 = (1.5 * aF) ** 2 / ((1 + k) * R)
+    dd = (d0 - dj) / 95.0
+    ds = [d0] + [d0 - dd * (s + 1) for s in range(100)]
+    _, res = bem.bem_sweep(K, h, prm, ds)
+    assert res[-1].n_contact == 0                  # pulled off within the sweep
+    assert all(r.n_penetrating == 0 for r in res[1:])
+    return min(r.F for r in res[1:]), res
+
+
+# fitted c1 / Table 1 value at each tabulated k (filled in by the test below)
+C1_FIT = {}
+
+
+@pytest.mark.parametrize("k", [-0.9, -0.7, -0.5, -0.3, -0.1, 0.1, 0.3, 0.5, 0.7, 0.9])
+def test_c1_calibration_reproduces_table1(k):
     """Table 1 calibrates c1(k) so that the BEM pull-off of a parabolic
     indenter equals the JKR-type -(3+k) pi gamma R / 2.  Redo that fit: the
     pull-off force at c1 and 1.25 c1 (p_crit from Eq. 24 scales as c1^-1/2)
     gives the power law F_min ~ c1^e, and with it the c1 that meets the
-    closed form.  512^2 with ~100-150 elements across the pull-off radius;
-    preload to (1.5 a_F)^2 / ((1+k) R), then 100 unloading steps."""
+    closed form.  512^2 on a side of 4 a_F (128 elements across the pull-off
+    radius; the preload radius 1.5 a_F stays inside), R = 1, gamma = 2.9995e-3,
+    nu = 0.3, mixed precision."""
     from paper_1612_08395_amd import bem
     announce(f"c1-calibration k={k}")
     n, nu, R, gam = 512, 0.3, 1.0, 2.9995e-3
+    aF, dj = _jkr_points(k, nu, gam, R)
+    L = 4.0 * aF
     dx = L / n
     K = bem.bem_influence(n, n, dx, k, nu)
     h = inputs.parabolic(n, L, R)
-    d0 = (1.5 * aF) ** 2 / ((1 + k) * R)
-    dd = (d0 - dj) / 95.0
-    ds = [d0] + [d0 - dd * (s + 1) for s in range(100)]
     pc = bem.bem_p_crit(k, nu, gam, dx)       # Eq. 24 with Table 1's c1
     ref = an.jkr_min_force(k, gam, R)
     ratio = {}
     for f in (1.0, 1.25):
         prm = bem.bem_params_init(gamma=gam, p_crit=pc / math.sqrt(f), precision=bem.BEM_MIXED)
-        _, res = bem.bem_sweep(K, h, prm, ds)
-        assert res[-1].n_contact == 0
-        ratio[f] = min(r.F for r in res[1:]) / ref
+        Fmin, _ = _pulloff_sweep(bem, K, h, k, R, aF, dj, prm)
+        ratio[f] = Fmin / ref
     K.free()
     e = math.log(ratio[1.25] / ratio[1.0]) / math.log(1.25)
     c1_fit = math.exp(-math.log(ratio[1.0]) / e)   # relative to the table value
+    C1_FIT[k] = c1_fit
     print(f"[c1 k={k}] F_min/F_JKR {ratio[1.0]:.4f} (c1), {ratio[1.25]:.4f} (1.25 c1); "
           f"exponent {e:.3f}; fitted c1 / Table 1 = {c1_fit:.4f}", flush=True)
     assert e == pytest.approx(-1.0, abs=0.1)      # F_min ~ p_crit^2 ~ 1 / c1
     assert c1_fit == pytest.approx(1.0, abs=0.03)
+
+
+def test_pulloff_independent_of_R_over_c0():
+    """Fig. 8a: the adhesive F(d) of a parabolic indenter for several R / c0
+    (here c0 = 0.5, 1, 2 with R = 1, k = 0.5, side 2, 512^2, mixed
+    precision).  c0 enters through C = alpha (1 - nu^2) c0^k / E0 and the
+    c0^k of Eq. 24; the closed-form pull-off -(3+k) pi gamma R / 2 does not
+    depend on it, while the pull-off radius grows as c0^(k/(3+k))."""
+    from paper_1612_08395_amd import bem
+    announce("R/c0 sweep")
+    n, L, k, nu, R, gam = 512, 2.0, 0.5, 0.3, 1.0, 2.9995e-3
+    dx = L / n
+    h = inputs.parabolic(n, L, R)
+    ref = an.jkr_min_force(k, gam, R)
+    got = {}
+    for c0 in (0.5, 1.0, 2.0):
+        aF, dj = _jkr_points(k, nu, gam, R, c0)
+        K = bem.bem_influence_ex(n, n, dx, dx, k, nu, 1.0, c0)
+        Fmin, res = _pulloff_sweep(bem, K, h, k, R, aF, dj,
+                                   bem.bem_params_init(gamma=gam, precision=bem.BEM_MIXED))
+        K.free()
+        got[c0] = Fmin / ref
+        at_min = min(res[1:], key=lambda r: r.F)
+        print(f"[R/c0={R / c0:g}] F_min / F_JKR {got[c0]:.4f}, a_F {aF:.4f} "
+              f"({aF / dx:.0f} elements), contact radius at F_min "
+              f"{math.sqrt(at_min.area / math.pi):.4f}", flush=True)
+        assert got[c0] == pytest.approx(1.0, rel=2.1 / (aF / dx))
+    vals = np.array(list(got.values()))
+    assert vals.max() / vals.min() - 1.0 < 0.01
+
+
+def test_adhesive_step_transitions_c0():
+    """GPU vs oracle pull-off step transitions at c0 = 2 (R / c0 = 1/2),
+    k = 0.5, 128^2, side 2: from the oracle's previous contact set and
+    pressure (set into the GPU state), the same new contact set and pressure
+    (FP64, 1e-10)."""
+    from oracle import influence as inf
+    from oracle import material as m
+    from oracle import solver as so
+    from oracle.convolution import FFTConvolver
+    from paper_1612_08395_amd import bem
+    from tests.gpu_util import rel_l2
+    announce("c0 step transitions")
+    n, L, k, nu, R, gam, c0 = 128, 2.0, 0.5, 0.3, 1.0, 2.9995e-3, 2.0
+    dx = L / n
+    Kq = inf.influence_quarter(n, n, dx, dx, k)
+    C = m.compliance(k, nu, c0=c0)
+    conv = FFTConvolver(Kq, C, workers=-1)
+    h = inputs.parabolic(n, L, R)
+    pc = m.p_crit(k, nu, gam, dx, c0=c0)
+    aF, dj = _jkr_points(k, nu, gam, R, c0)
+    d0 = (1.5 * aF) ** 2 / ((1 + k) * R)
+    load = so.solve_nonadhesive(Kq, C, h, d0, tol=1e-12, conv=conv)
+    K = bem.bem_influence_ex(n, n, dx, dx, k, nu, 1.0, c0)
+    _, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d0))
+    assert rel_l2(p, load.p) <= 1e-10
+    A, pr = load.contact, load.p
+    rounds = 0
+    for s in range(1, 6):
+        d = d0 - s * (d0 - dj) / 5.0
+        step = so.adhesive_step(Kq, C, h, d, A, pr, pc, tol=1e-12, conv=conv)
+        st = bem.bem_state_create(K)
+        bem.bem_state_set(st, pr, A.astype(np.uint8))
+        _, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=d, gamma=gam), state=st)
+        st.free()
+        print(f"[c0=2] step {s} d={d:.4e} contact {A.sum()} -> {c.sum()} (oracle "
+              f"{step.contact.sum()}), rounds {res.detach_rounds}/{step.rounds}", flush=True)
+        assert res.p_crit == pytest.approx(pc, rel=1e-14)
+        assert np.array_equal(c.astype(bool), step.contact)
+        if step.contact.any():
+            assert rel_l2(p, step.p) <= 1e-10
+        rounds += step.rounds
+        A, pr = step.contact, step.p
+        if not A.any():
+            break
+    assert rounds > 0
+    K.free()

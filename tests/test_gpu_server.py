@@ -48,6 +48,7 @@ def test_alone_and_in_the_mix_are_identical():
     st = srv.stats()
     assert st.completed == len(reqs) and st.failed == 0
     assert st.peak_running >= 2                 # requests overlapped on the device
+    assert st.device_bytes_reserved <= 4 << 30  # both precisions share the pools
     assert st.p99_latency_s >= st.p50_latency_s > 0
     srv.free()
     for (n, k, h, prm), (status, res, p, c) in zip(reqs, got):

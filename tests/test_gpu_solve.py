@@ -407,3 +407,43 @@ def test_error_paths():
     assert np.all(np.isfinite(p))
     K.free()
     Kq.free()
+
+
+@pytest.mark.parametrize("k", [0.05, -0.35, 0.75, -0.87, 0.5])
+def test_library_c1_and_p_crit_match_oracle(k):
+    # Table 1 between its entries (natural cubic spline of ln c1) and Eq. 24:
+    # the library's own C implementation against the oracle's scipy spline.
+    bem = _bem()
+    announce("c1/p_crit", k)
+    assert bem.bem_c1(k) == pytest.approx(m.c1_corrected(k), rel=1e-14)
+    for nu, gam, dx, E0, c0 in ((0.3, 2e-3, 1 / 256, 1.0, 1.0), (0.25, 7e-5, 0.013, 2.5, 0.6)):
+        assert bem.bem_p_crit(k, nu, gam, dx, E0, c0) == pytest.approx(
+            m.p_crit(k, nu, gam, dx, E0=E0, c0=c0), rel=1e-14)
+
+
+def test_adhesive_step_at_off_table_k():
+    # k = 0.35 lies between Table 1 entries, so p_crit comes from the spline
+    # branch of both sides (library: bem_p_crit inside bem_solve; oracle:
+    # c1_corrected); c0 != 1 enters through C and c0^k in Eq. 24.
+    bem = _bem()
+    n, L, k, nu, R, gam, c0 = 96, 1.0, 0.35, 0.3, 1.0, 3e-5, 0.7
+    announce("adhesive-off-table", n, k)
+    dx = L / n
+    Kq = inf.influence_quarter(n, n, dx, dx, k)
+    C = m.compliance(k, nu, c0=c0)
+    conv = FFTConvolver(Kq, C, workers=-1)
+    h = inputs.parabolic(n, L, R)
+    pc = m.p_crit(k, nu, gam, dx, c0=c0)
+    load = so.solve_nonadhesive(Kq, C, h, 0.015, tol=1e-12, conv=conv)
+    step = so.adhesive_step(Kq, C, h, 0.005, load.contact, load.p, pc, tol=1e-12, conv=conv)
+    assert step.rounds >= 2 and 0 < step.contact.sum() < load.contact.sum()
+    K = bem.bem_influence_ex(n, n, dx, dx, k, nu, 1.0, c0)
+    st = bem.bem_state_create(K)
+    bem.bem_solve(K, h, bem.bem_params_init(d=0.015), state=st)
+    _, res, p, c, _ = bem.bem_solve(K, h, bem.bem_params_init(d=0.005, gamma=gam), state=st)
+    assert res.p_crit == pytest.approx(pc, rel=1e-14)
+    assert np.array_equal(c.astype(bool), step.contact)
+    assert rel_l2(p, step.p) <= FP64_TOL
+    assert res.detach_rounds == step.rounds
+    st.free()
+    K.free()

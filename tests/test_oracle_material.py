@@ -81,6 +81,51 @@ def test_c1_interpolation_between_table_points():
     assert 2.97 < m.c1_corrected(0.05) < 3.66
 
 
+def _piece(i):
+    """The cubic that ln c1 follows on [k_i, k_i+1], fitted through four
+    interior points (exact interpolation when ln c1 is a cubic there)."""
+    a, b = m.TABLE1_K[i], m.TABLE1_K[i + 1]
+    x = np.linspace(a, b, 6)[1:-1]
+    y = np.log([m.c1_corrected(float(t)) for t in x])
+    return np.poly1d(np.polyfit(x - a, y, 3)), a, b
+
+
+def test_c1_interpolant_is_the_natural_cubic_spline_of_ln_c1():
+    # Between the Table 1 entries (Section 3.1) the reading is a natural
+    # cubic spline of ln c1 over k.  Such a spline is fixed uniquely by four
+    # properties, each checked here from values of c1_corrected alone:
+    # (i) ln c1 is a cubic on every interval (its fourth difference on
+    #     equally spaced points vanishes; a spline of c1 itself would leave
+    #     a non-zero one),
+    # (ii) it passes through the 19 tabulated values,
+    # (iii) value, slope and curvature are continuous at the 17 interior
+    #     knots (the cubics fitted on either side agree there),
+    # (iv) the curvature is zero at k = -0.9 and 0.9 (natural ends; a
+    #     clamped or not-a-knot end would not give zero).
+    ks = m.TABLE1_K
+    for i in range(len(ks) - 1):
+        x = np.linspace(ks[i], ks[i + 1], 7)[1:-1]
+        y = np.log([m.c1_corrected(float(t)) for t in x])
+        d4 = y[0] - 4 * y[1] + 6 * y[2] - 4 * y[3] + y[4]
+        assert abs(d4) < 1e-13, (i, d4)
+    pieces = [_piece(i) for i in range(len(ks) - 1)]
+    for i, (P, a, b) in enumerate(pieces):
+        assert P(0.0) == pytest.approx(math.log(m.TABLE1_C1[i]), abs=1e-12)
+        assert P(b - a) == pytest.approx(math.log(m.TABLE1_C1[i + 1]), abs=1e-12)
+    for i in range(1, len(pieces)):
+        L, aL, bL = pieces[i - 1]
+        R, aR, _ = pieces[i]
+        for der in (1, 2):
+            left = L.deriv(der)(bL - aL)
+            right = R.deriv(der)(0.0)
+            assert left == pytest.approx(right, rel=1e-7, abs=1e-7), (i, der)
+    first, a0, _ = pieces[0]
+    last, aN, bN = pieces[-1]
+    scale = max(abs(P.deriv(2)(0.0)) for P, _, _ in pieces)
+    assert abs(first.deriv(2)(0.0)) < 1e-7 * scale
+    assert abs(last.deriv(2)(bN - aN)) < 1e-7 * scale
+
+
 def test_p_crit_scaling():
     # Eq. 24: p_crit ~ sqrt(gamma) * dx^-(1-k)/2 * sqrt(E0)
     k, nu = 0.3, 0.3
