@@ -359,6 +359,10 @@ def adhesive_4096(bem, torch, n_load=10, n_unload=10):
             _, r = bem.bem_solve_dev(K, h_dev, prm, state=st, p_out=p)
             ps.append(p)
             rs.append(r.as_dict())
+            torch.cuda.synchronize()
+            log(f"[adhesive-4096] {name} step {i} d={d:.4e} F={r.F:.4e} contact={r.n_contact} "
+                f"iters={r.iters} rounds={r.detach_rounds} status={r.status} "
+                f"t={time.perf_counter() - t0:.1f}s")
         torch.cuda.synchronize()
         runs[name] = (time.perf_counter() - t0, ps, rs)
         st.free()
