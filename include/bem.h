@@ -114,6 +114,25 @@ int bem_convolve(bem_influence_t K, const double* p, double* u, void* stream);
  */
 int bem_convolve_dev(bem_influence_t K, int precision, const void* p, void* u, void* stream);
 
+/*
+ * bem_convolve_dev_noalloc -- bem_convolve_dev for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results, with the
+ * row spectrum in a fixed array of BEM_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, so the call makes
+ * no allocation of any kind.  The caller still passes p and u (device arrays
+ * as for bem_convolve_dev).  The handle's device must be current.
+ * Errors: BEM_EINVAL (NULL argument, bad precision, another device current),
+ * BEM_EUNSUPPORTED when ny * Lx complex values of the precision (Lx = Mx / 2,
+ * bem_influence_info) exceed BEM_NOALLOC_SCRATCH_BYTES (16 MiB: up to
+ * 1024 x 1024 in FP64, 2048 x 1024 in FP32), BEM_EDEVICE.
+ * All calls on one device share the array: calls that overlap on a device
+ * (other streams, other threads) race and must be ordered by the caller.
+ */
+#define BEM_NOALLOC_SCRATCH_BYTES (16 << 20)
+int bem_convolve_dev_noalloc(bem_influence_t K, int precision, const void* p, void* u,
+                             void* stream);
+
 /* ---------------------------------------------------------------------------
  * Contact solves
  * ------------------------------------------------------------------------- */

@@ -68,6 +68,8 @@ _f_influence_info = _sig("bem_influence_info", _c_int, [_vp, ctypes.POINTER(Infl
 _f_influence_coeffs = _sig("bem_influence_coeffs", _c_int, [_vp, _dp])
 _f_convolve = _sig("bem_convolve", _c_int, [_vp, _dp, _dp, _vp])
 _f_convolve_dev = _sig("bem_convolve_dev", _c_int, [_vp, _c_int, _vp, _vp, _vp])
+_f_convolve_dev_noalloc = _sig("bem_convolve_dev_noalloc", _c_int, [_vp, _c_int, _vp, _vp, _vp])
+BEM_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 def bem_last_error():
@@ -165,6 +167,10 @@ def bem_convolve(K, p, stream=None):
 
 def bem_convolve_dev(K, precision, p, u, stream=None):
     _check(_f_convolve_dev(K.handle, int(precision), _ptr(p), _ptr(u), _stream(stream)))
+
+
+def bem_convolve_dev_noalloc(K, precision, p, u, stream=None):
+    _check(_f_convolve_dev_noalloc(K.handle, int(precision), _ptr(p), _ptr(u), _stream(stream)))
 
 
 # ---- contact solves ----------------------------------------------------------
