@@ -328,7 +328,10 @@ def big_grid(bem, torch, depths_n=5):
 
 # Adhesive leg of the 4096^2 workload: work of adhesion 1e-4 E0 L (the third
 # of the four values {1, 3, 10, 30} 1e-5 the crop tests sweep), 10 loading
-# depths up to D10_4096, then 10 pull-off steps down to -D10_4096 / 4.
+# depths up to D10_4096, then 10 pull-off steps of D10_4096 / 20 down to half
+# of it.  (Further down the detachment front needs hundreds of detach rounds
+# per step: a full pull-off of this grid takes minutes in MIXED and far
+# longer in FP64, beyond a bench leg.)
 GAMMA_4096 = 1e-4
 
 
@@ -342,7 +345,7 @@ def adhesive_4096(bem, torch, n_load=10, n_unload=10):
     n, h_dev, K = big_grid_setup(bem, torch)
     dq = D10_4096
     depths = [dq * s / n_load for s in range(1, n_load + 1)]
-    depths += [dq * (1.0 - s / (0.8 * n_unload)) for s in range(1, n_unload + 1)]
+    depths += [dq * (1.0 - 0.5 * s / n_unload) for s in range(1, n_unload + 1)]
     out = {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395, "gamma": GAMMA_4096,
            "p_crit": bem.bem_p_crit(-0.3, 0.25, GAMMA_4096, L / n),
            "depths": [float(f"{d:.6e}") for d in depths]}

@@ -307,18 +307,30 @@ typedef struct {
   double mean_wait_s;                   /* submit -> start */
   double solves_per_s;                  /* completed / (last completion - first submit) */
   long long device_bytes_reserved, cache_entries, cache_hits, cache_misses, evictions;
+  long long batched;                    /* completed on the batched path */
+  double mean_batch_slots;              /* mean solves per batched launch chunk */
 } bem_server_stats_t;
 
 /*
- * bem_server_create -- a request loop with n_slots (1..16) concurrent solves,
- * each on its own non-blocking HIP stream of the current device, and a
+ * bem_server_create_ex -- a request loop on the current device with a
  * device-memory budget for cached influence operators plus solver states
- * (bem_footprint).  Each request is a cold-start bem_solve of its own;
- * requests run concurrently on the GPU and a queued request starts as soon
- * as a slot is free and the budget admits it (FIFO; idle cache entries are
- * evicted least-recently-used).  The result of a request does not depend
- * on what else runs.
+ * (bem_footprint); a queued request starts as soon as the budget admits it
+ * (idle cache entries are evicted least-recently-used) and runs on the GPU
+ * together with the requests already in progress.
+ *  - Batched path (batch_slots > 0): displacement-controlled requests with
+ *    nx, ny <= 1024 are grouped by padded geometry and precision; each group
+ *    runs up to batch_slots solves whose conjugate-gradient kernels share
+ *    launches (one launch per kernel for all of them), admitting queued
+ *    requests as slots free up between chunks of iterations.
+ *  - Per-request path: every other request (larger grids, load control, or
+ *    all requests when batch_slots = 0) is a bem_solve of its own on one of
+ *    n_slots (1..16) worker threads, each with its own non-blocking stream.
+ * Every request is solved from a cold start with the kernels and order of
+ * bem_solve, so its result does not depend on what else runs.
+ * batch_slots: 0..64.
  */
+int bem_server_create_ex(long long budget_bytes, int n_slots, int batch_slots, bem_server_t* out);
+/* bem_server_create -- bem_server_create_ex with batch_slots = 16. */
 int bem_server_create(long long budget_bytes, int n_slots, bem_server_t* out);
 /* Queue a request; *id identifies it.  BEM_ENOMEM if it can never fit the
  * budget, BEM_EINVAL for a bad grid. */

@@ -398,7 +398,8 @@ class ServerStats(ctypes.Structure):
                 ("mean_wait_s", _c_double), ("solves_per_s", _c_double),
                 ("device_bytes_reserved", ctypes.c_longlong),
                 ("cache_entries", ctypes.c_longlong), ("cache_hits", ctypes.c_longlong),
-                ("cache_misses", ctypes.c_longlong), ("evictions", ctypes.c_longlong)]
+                ("cache_misses", ctypes.c_longlong), ("evictions", ctypes.c_longlong),
+                ("batched", ctypes.c_longlong), ("mean_batch_slots", _c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -409,6 +410,8 @@ _f_state_reset = _sig("bem_state_reset", _c_int, [_vp])
 _f_footprint = _sig("bem_footprint", _c_int, [_c_int, _c_int, _c_int, _llp, _llp])
 _f_server_create = _sig("bem_server_create", _c_int, [ctypes.c_longlong, _c_int,
                                                       ctypes.POINTER(_vp)])
+_f_server_create_ex = _sig("bem_server_create_ex", _c_int, [ctypes.c_longlong, _c_int, _c_int,
+                                                            ctypes.POINTER(_vp)])
 _f_server_submit = _sig("bem_server_submit", _c_int, [_vp, ctypes.POINTER(Request), _llp])
 _f_server_poll = _sig("bem_server_poll", _c_int, [_vp, ctypes.c_longlong, _c_int,
                                                   ctypes.POINTER(Result), ctypes.POINTER(_c_int)])
@@ -431,9 +434,13 @@ class Server:
     """Owning wrapper of bem_server_t.  Keeps each submitted request's host
     arrays alive until the request has been polled."""
 
-    def __init__(self, budget_bytes, n_slots):
+    def __init__(self, budget_bytes, n_slots, batch_slots=None):
         h = _vp()
-        _check(_f_server_create(int(budget_bytes), int(n_slots), ctypes.byref(h)))
+        if batch_slots is None:
+            _check(_f_server_create(int(budget_bytes), int(n_slots), ctypes.byref(h)))
+        else:
+            _check(_f_server_create_ex(int(budget_bytes), int(n_slots), int(batch_slots),
+                                       ctypes.byref(h)))
         self._h = h
         self._keep = {}
 
@@ -487,3 +494,7 @@ class Server:
 
 def bem_server_create(budget_bytes, n_slots):
     return Server(budget_bytes, n_slots)
+
+
+def bem_server_create_ex(budget_bytes, n_slots, batch_slots):
+    return Server(budget_bytes, n_slots, batch_slots)

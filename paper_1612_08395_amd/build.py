@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libbem.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["influence.hip", "conv.hip", "cg_f32.hip", "cg_f64.hip", "api.cpp", "handles.cpp",
-           "solve.cpp", "server.cpp", "clock.cpp", "noalloc.hip"]
+           "solve.cpp", "server.cpp", "clock.cpp", "noalloc.hip", "batch_f32.hip",
+           "batch_f64.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -49,47 +49,11 @@
 // in slots indexed by it & 1.  Every kernel returns at once when `done` is
 // set, so the host may queue several iterations and check the flag rarely.
 #pragma once
+#include "cg_api.h"
 #include "common.h"
 #include "conv_kernels.h"
 
 namespace bem {
-
-struct CgScal {
-  double tol;
-  int max_iter, stall_limit;
-  // K4, workgroup 0, slot it & 1
-  double G_hist[2], best_hist[2];
-  int stall_hist[2];
-  // decision record (written once, when done is set)
-  int done, status, iter, pad_;
-  double G, rhs2, sum_p;
-  // final sums of the elementwise kernels
-  double fin_sum_p, fin_contact, fin_pen, fin_detach;
-  unsigned int ticket[8];
-  // load control: prescribed sum of p (F / (dx dy)); K4 history (slot
-  // it & 1) of the mean gap over Ic, the load scale and |Ic|; values at the
-  // stopping iteration
-  double W;
-  double gbar_hist[2], scale_hist[2], nc_hist[2];
-  double gbar, scale;
-};
-
-enum { CG_DISP = 0, CG_FIXED = 1, CG_FORCE = 2 };
-
-enum { CG_ST_OK = 0, CG_ST_NOCONV = 1, CG_ST_FLOOR = 2, CG_ST_NUMERIC = -5 };
-
-// partial-sum slots inside the `part` allocation
-constexpr int kMaxRowBlocks = 2048;
-constexpr int kPartUpd = 0;                      // 3 values: sum|dp|, sum|p|, n_ol
-constexpr int kPartGap = 3 * kMaxRowBlocks;      // 2 values: sum_Ic g^2, sum_Ic (h-d)^2
-                                                 // load control, 4: sum_Ic e, sum_Ic e^2,
-                                                 // |Ic|, sum_Ic u^2 (e = g - previous gbar)
-constexpr int kPartDots = 7 * kMaxRowBlocks;     // 1 value: sum g t (K4); load control,
-                                                 // 4 (K6): sum g t, sum r t, sum t, sum_Ic r
-constexpr int kMaxColBlocks = 4096;
-constexpr int kPartRT = 11 * kMaxRowBlocks;      // 1 value per column workgroup: sum t r
-constexpr int kPartElem = kPartRT + kMaxColBlocks;   // elementwise kernels (3 values x 1024)
-constexpr int kPartTotal = kPartElem + 3 * 1024;
 
 // Block sums of NV values (result in every thread), one barrier pair.
 template <int NV, int NTHR>
@@ -116,13 +80,16 @@ __device__ __forceinline__ void block_sum_n(double (&v)[NV], double* red) {
   __syncthreads();
 }
 
-// This workgroup's partials (plain stores; read by later kernels).
+// This workgroup's partials (plain stores; read by later kernels).  bid:
+// the workgroup's index within its problem (blockIdx.x, or the index inside
+// its slot in a batched launch).
 template <int NV, int NTHR>
-__device__ __forceinline__ void write_partials(double (&acc)[NV], double* red, double* part) {
+__device__ __forceinline__ void write_partials(double (&acc)[NV], double* red, double* part,
+                                               int bid) {
   block_sum_n<NV, NTHR>(acc, red);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[blockIdx.x * NV + k] = acc[k];
+    for (int k = 0; k < NV; ++k) part[bid * NV + k] = acc[k];
 }
 
 // Totals of the nb partials an earlier kernel wrote (same order everywhere).
@@ -269,7 +236,7 @@ struct UpdatePro {
     }
   }
   template <int NTHR>
-  __device__ bool decide(double* red) {
+  __device__ bool decide(double* red, int bid) {
     a_dp = a_p = a_ol = 0.0;
     double tot[NVD];
     dots.template total<NTHR>(part + kPartDots, nb, red, tot);
@@ -348,9 +315,9 @@ struct UpdatePro {
     }
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
+  __device__ void finish(double* red, int bid) {
     double acc[3] = {a_dp, a_p, a_ol};
-    write_partials<3, NTHR>(acc, red, part + kPartUpd);
+    write_partials<3, NTHR>(acc, red, part + kPartUpd, bid);
   }
 };
 
@@ -439,8 +406,8 @@ struct GapEpi {
     }
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
-    write_partials<NV, NTHR>(acc, red, part + kPartGap);
+  __device__ void finish(double* red, int bid) {
+    write_partials<NV, NTHR>(acc, red, part + kPartGap, bid);
   }
 };
 
@@ -499,7 +466,7 @@ struct DirPro {
     }
   }
   template <int NTHR>
-  __device__ bool decide(double* red) {
+  __device__ bool decide(double* red, int bid) {
     double up[3], gp[NVG];
     pu.template total<NTHR>(part + kPartUpd, nb, red, up);
     pg.template total<NTHR>(part + kPartGap, nb, red, gp);
@@ -542,7 +509,7 @@ struct DirPro {
         status = CG_ST_FLOOR;
       }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       if constexpr (FC) {
         sc->gbar_hist[it & 1] = gbar;
         sc->scale_hist[it & 1] = scale;
@@ -593,10 +560,10 @@ struct DirPro {
     }
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
+  __device__ void finish(double* red, int bid) {
     if constexpr (!FC) {
       double acc[1] = {a_gt};
-      write_partials<1, NTHR>(acc, red, part + kPartDots);
+      write_partials<1, NTHR>(acc, red, part + kPartDots, bid);
     }
   }
 };
@@ -663,8 +630,8 @@ struct DotsEpi {
     }
   }
   template <int NTHR>
-  __device__ void finish(double* red) {
-    write_partials<NV, NTHR>(acc, red, part + kPartDots);
+  __device__ void finish(double* red, int bid) {
+    write_partials<NV, NTHR>(acc, red, part + kPartDots, bid);
   }
 };
 

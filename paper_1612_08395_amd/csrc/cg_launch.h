@@ -7,18 +7,6 @@
 
 namespace bem {
 
-template <typename T>
-struct CgBufs {
-  T* p;
-  T* t;
-  T* g;
-  T* hd;
-  uint8_t* mask;
-  cplx<T>* S;
-  double* part;
-  CgScal* sc;
-};
-
 inline int ew_blocks(size_t n) {
   size_t b = (n + EW_THREADS - 1) / EW_THREADS;
   if (b < 1) b = 1;

@@ -45,11 +45,12 @@ namespace bem {
 //    issue<NTHR>() -> false: the whole workgroup returns; else issues the
 //      loads of any partial sums the prologue needs;
 //    fetch<NTHR>(ya, yb, hasb, nx): issues the field loads;
-//    decide<NTHR>(red) -> false: the whole workgroup returns (reduces the
+//    decide<NTHR>(red, bid) -> false: the whole workgroup returns (reduces the
 //      partial sums; every workgroup reaches the same decision);
 //    make<NTHR>(ya, yb, hasb, nx, va, vb): values to transform (zero for
 //      n >= nx); commit<NTHR>(...): writes back updated state;
-//    finish<NTHR>(red): per-workgroup partial sums.
+//    finish<NTHR>(red, bid): per-workgroup partial sums (bid: the
+//      workgroup's index within its problem).
 //  epilogue (C2R): begin (may issue loads of partial sums), prefetch<NTHR>
 //    (ya, yb, hasb, nx) (issued before the transform so the loads overlap
 //    it), ready<NTHR>(red) (reductions the epilogue needs), consume<NTHR>(...,
@@ -72,7 +73,7 @@ struct PlainLoad {
     }
   }
   template <int NTHR>
-  __device__ bool decide(double*) { return true; }
+  __device__ bool decide(double*, int) { return true; }
   template <int NTHR>
   __device__ void make(int, int, bool, int, T (&va)[PER], T (&vb)[PER]) {
 #pragma unroll
@@ -84,7 +85,7 @@ struct PlainLoad {
   template <int NTHR>
   __device__ void commit(int, int, bool, int, const T (&)[PER], const T (&)[PER]) {}
   template <int NTHR>
-  __device__ void finish(double*) {}
+  __device__ void finish(double*, int) {}
 };
 
 template <typename T, int PER>
@@ -110,7 +111,7 @@ struct PlainStore {
     }
   }
   template <int NTHR>
-  __device__ void finish(double*) {}
+  __device__ void finish(double*, int) {}
 };
 
 template <int L, int NTHR>
@@ -129,19 +130,19 @@ struct min_waves_of<F, std::void_t<decltype(F::kMinWaves)>> {
   static constexpr int value = F::kMinWaves;
 };
 
+// Row sweep R2C of row pair bid (rows 2 bid, 2 bid + 1) of one problem.
 template <typename T, int L, int NTHR, class Pro>
-__global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro pro_arg, cplx<T>* __restrict__ S, int nx,
-                                                  int ny, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void row_r2c_body(Pro& pro, cplx<T>* __restrict__ S, int nx, int ny,
+                                             const cplx<T>* __restrict__ tw, int bid) {
   constexpr int STR = LdsLayout<T>::row_stride(L);
   constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
-  Pro pro = pro_arg;
   if (!pro.template issue<NTHR>()) return;
-  const int ya = 2 * blockIdx.x, yb = ya + 1;
+  const int ya = 2 * bid, yb = ya + 1;
   const bool hasb = yb < ny;
   pro.template fetch<NTHR>(ya, yb, hasb, nx);
-  if (!pro.template decide<NTHR>(red)) return;
+  if (!pro.template decide<NTHR>(red, bid)) return;
   T va[PER], vb[PER];
   pro.template make<NTHR>(ya, yb, hasb, nx, va, vb);
 #pragma unroll
@@ -180,7 +181,14 @@ __global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(Pro 
       if (hasb) Sb[k] = {half * (Z.y + Zp.y), half * (Zp.x - Z.x)};
     }
   }
-  pro.template finish<NTHR>(red);
+  pro.template finish<NTHR>(red, bid);
+}
+
+template <typename T, int L, int NTHR, class Pro>
+__global__ __launch_bounds__(NTHR, min_waves_of<Pro>::value) void k_row_r2c(
+    Pro pro_arg, cplx<T>* __restrict__ S, int nx, int ny, const cplx<T>* __restrict__ tw) {
+  Pro pro = pro_arg;
+  row_r2c_body<T, L, NTHR>(pro, S, nx, ny, tw, blockIdx.x);
 }
 
 // Guarded load of a complex value without control flow (see load_or0).
@@ -271,15 +279,14 @@ __device__ __forceinline__ void col_multiply(cplx<T>* lds, int c0, int lx, const
   }
 }
 
+// Column sweep of column group xcd_block(bid, nblk) of one problem.
 template <typename T, int LY, int W, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int lx, int ny,
-                                                   const T* __restrict__ KT, int kpitch,
-                                                   const cplx<T>* __restrict__ tw,
-                                                   const int* __restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void col_conv_body(cplx<T>* __restrict__ S, int lx, int ny,
+                                              const T* __restrict__ KT, int kpitch,
+                                              const cplx<T>* __restrict__ tw, int bid, int nblk) {
   constexpr int STR = LdsLayout<T>::col_stride(LY);
   __shared__ cplx<T> lds[2 * W * STR];
-  const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
+  const int c0 = xcd_block(bid, nblk) * W;
   using Stage = ColStage<T, LY, W, NTHR>;
   {
     Stage st;
@@ -314,6 +321,15 @@ __global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int 
       S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
 }
 
+template <typename T, int LY, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_col_conv(cplx<T>* __restrict__ S, int lx, int ny,
+                                                   const T* __restrict__ KT, int kpitch,
+                                                   const cplx<T>* __restrict__ tw,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  col_conv_body<T, LY, W, NTHR>(S, lx, ny, KT, kpitch, tw, blockIdx.x, gridDim.x);
+}
+
 // Spectral energy of the packed half spectrum.  After the forward column
 // transform, the full padded spectrum T(kx, ky) of a real field is known from
 // columns kx = 1 .. Lx-1 (each also stands for Mx - kx) and from the packed
@@ -337,16 +353,14 @@ __device__ __forceinline__ double energy_packed(cplx<T> z, cplx<T> zm, T k0, T k
 // inverse transforms of a convolution whose only use is that inner product.
 // One FP64 partial per workgroup into part[blockIdx.x].
 template <typename T, int LY, int W, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__ S, int lx, int ny,
-                                                     const T* __restrict__ KT, int kpitch,
-                                                     const cplx<T>* __restrict__ tw,
-                                                     const int* __restrict__ done,
-                                                     double* __restrict__ part) {
-  if (done && *done) return;
+__device__ __forceinline__ void col_energy_body(const cplx<T>* __restrict__ S, int lx, int ny,
+                                                const T* __restrict__ KT, int kpitch,
+                                                const cplx<T>* __restrict__ tw,
+                                                double* __restrict__ part, int bid, int nblk) {
   constexpr int STR = LdsLayout<T>::col_stride(LY);
   __shared__ cplx<T> lds[2 * W * STR];
   __shared__ double red[64];
-  const int c0 = xcd_block(blockIdx.x, gridDim.x) * W;
+  const int c0 = xcd_block(bid, nblk) * W;
   {
     using Stage = ColStage<T, LY, W, NTHR>;
     Stage st;
@@ -382,19 +396,29 @@ __global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__
     }
   }
   e = block_sum<NTHR>(e, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = e;
+  if (threadIdx.x == 0) part[bid] = e;
 }
 
+template <typename T, int LY, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_col_energy(const cplx<T>* __restrict__ S, int lx, int ny,
+                                                     const T* __restrict__ KT, int kpitch,
+                                                     const cplx<T>* __restrict__ tw,
+                                                     const int* __restrict__ done,
+                                                     double* __restrict__ part) {
+  if (done && *done) return;
+  col_energy_body<T, LY, W, NTHR>(S, lx, ny, KT, kpitch, tw, part, blockIdx.x, gridDim.x);
+}
+
+// Row sweep C2R of row pair bid of one problem.
 template <typename T, int L, int NTHR, class Epi>
-__global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
-                                                  const cplx<T>* __restrict__ tw, Epi epi_arg) {
+__device__ __forceinline__ void row_c2r_body(const cplx<T>* __restrict__ S, int nx, int ny,
+                                             const cplx<T>* __restrict__ tw, Epi& epi, int bid) {
   constexpr int STR = LdsLayout<T>::row_stride(L);
   constexpr int PER = row_per<L, NTHR>();
   __shared__ cplx<T> lds[2 * STR];
   __shared__ double red[64];
-  Epi epi = epi_arg;
   if (!epi.template begin<NTHR>(red)) return;
-  const int ya = 2 * blockIdx.x, yb = ya + 1;
+  const int ya = 2 * bid, yb = ya + 1;
   const bool hasb = yb < ny;
   const cplx<T>* Sa = S + (size_t)ya * L;
   const cplx<T>* Sb = S + (size_t)yb * L;
@@ -444,7 +468,14 @@ __global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S,
     vb[q] = z.y;
   }
   epi.template consume<NTHR>(ya, yb, hasb, nx, va, vb);
-  epi.template finish<NTHR>(red);
+  epi.template finish<NTHR>(red, bid);
+}
+
+template <typename T, int L, int NTHR, class Epi>
+__global__ __launch_bounds__(NTHR) void k_row_c2r(const cplx<T>* __restrict__ S, int nx, int ny,
+                                                  const cplx<T>* __restrict__ tw, Epi epi_arg) {
+  Epi epi = epi_arg;
+  row_c2r_body<T, L, NTHR>(S, nx, ny, tw, epi, blockIdx.x);
 }
 
 // Forward column transform of the (FP64) row spectrum of Q, and the real,

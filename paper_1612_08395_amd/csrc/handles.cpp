@@ -59,14 +59,15 @@ int influence_build(bem_influence_s* h) {
   if ((e = launch_influence(h->Kq, h->nx, h->ny, h->dx, h->dy, h->k, s)) != hipSuccess)
     return hip_fail(e, "influence coefficients");
 
-  cplx<double>* S = nullptr;
-  e = hipMalloc((void**)&S, (size_t)h->ny * g.Lx * sizeof(cplx<double>));
-  if (e != hipSuccess) return hip_fail(e, "spectrum scratch");
+  // the spectrum is built in the handle's FP64 convolution scratch, which
+  // the handle keeps (a free here would wait for the whole device)
+  if ((rc = dev_alloc(h, (void**)&h->S64, (size_t)h->ny * g.Lx * sizeof(cplx<double>),
+                      "spectrum scratch")))
+    return rc;
   const double scale = h->C / ((double)Mx * (double)My);
-  e = launch_spectrum(g, h->Kq, S, h->twx64, h->twy64, h->KT64, h->KT32, scale, s);
+  e = launch_spectrum(g, h->Kq, h->S64, h->twx64, h->twy64, h->KT64, h->KT32, scale, s);
   hipError_t e2 = hipMemcpyAsync(&h->K00, h->Kq, sizeof(double), hipMemcpyDeviceToHost, s);
   hipError_t e3 = hipStreamSynchronize(s);
-  hipFree(S);
   if (e != hipSuccess) return hip_fail(e, "kernel spectrum");
   if (e2 != hipSuccess) return hip_fail(e2, "kernel spectrum");
   if (e3 != hipSuccess) return hip_fail(e3, "influence build");

@@ -166,7 +166,7 @@ struct QLoad {
     }
   }
   template <int NTHR>
-  __device__ bool decide(double*) { return true; }
+  __device__ bool decide(double*, int) { return true; }
   template <int NTHR>
   __device__ void make(int, int, bool, int, double (&va)[PER], double (&vb)[PER]) {
 #pragma unroll
@@ -178,7 +178,7 @@ struct QLoad {
   template <int NTHR>
   __device__ void commit(int, int, bool, int, const double (&)[PER], const double (&)[PER]) {}
   template <int NTHR>
-  __device__ void finish(double*) {}
+  __device__ void finish(double*, int) {}
 };
 
 hipError_t launch_twiddles(cplx<double>* t64, cplx<float>* t32, int M, hipStream_t s) {

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/bem.h"
+#include "cg_api.h"
 #include "launch.h"
 
 struct bem_influence_s {
@@ -33,7 +35,39 @@ struct bem_influence_s {
   double* epart = nullptr;   // partials of the spectral-energy sweep (timing hook)
 };
 
+// Solver state: device buffers of one solve and its warm-start data.
+struct bem_state_s {
+  bem_influence_s* K = nullptr;
+  size_t n = 0;
+  int precision = -1;  // precision of the T buffers below (-1: none yet)
+  void* p = nullptr;
+  void* t = nullptr;
+  void* g = nullptr;
+  void* hd = nullptr;
+  void* S = nullptr;
+  uint8_t* mask = nullptr;
+  double* h64 = nullptr;
+  double* out64 = nullptr;
+  double* part = nullptr;
+  bem::CgScal* sc = nullptr;
+  bem::CgScal* sc_host = nullptr;  // pinned
+  bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
+  // g = C K * p + h - g_d for the current p (set by a displacement-controlled
+  // solve; a sweep's next step at another d starts from it, same h)
+  bool g_valid = false;
+  double g_d = 0.0;
+  long long device_bytes = 0;
+  int last_iters[3] = {0, 0, 0};  // iterations of the previous CG solve, per mode
+};
+
 namespace bem {
+
+// solve.cpp: typed buffers for a precision; Eq. 24 parameter checks; status
+// mapping and combination.
+int ensure_precision(bem_state_s* st, int precision, hipStream_t s);
+int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, double* pcrit);
+int status_code(int cg_status);
+int worse(int a, int b);
 
 int set_error(int code, const char* fmt, ...);
 void clear_error();

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_r2c_w(Pro pro_arg,
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
   pro.template fetch<NTHR>(ya, yb, hasb, nx);
-  if (!pro.template decide<NTHR>(red)) return;
+  if (!pro.template decide<NTHR>(red, blockIdx.x)) return;
   float va[PER], vb[PER];
   pro.template make<NTHR>(ya, yb, hasb, nx, va, vb);
 #pragma unroll
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_r2c_w(Pro pro_arg,
     Sa[k] = a;
     if (hasb) Sb[k] = b;
   }
-  pro.template finish<NTHR>(red);
+  pro.template finish<NTHR>(red, blockIdx.x);
 }
 
 template <int L, class Epi>
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_c2r_w(const cplx<flo
     vb[q] = in ? z.y : 0.f;
   }
   epi.template consume<NTHR>(ya, yb, hasb, nx, va, vb);
-  epi.template finish<NTHR>(red);
+  epi.template finish<NTHR>(red, blockIdx.x);
 }
 
 // Row sweep launchers: the wave kernels when WAVE is set (FP32, Lx = 2048,

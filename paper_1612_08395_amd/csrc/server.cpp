@@ -1,19 +1,30 @@
 // Serving loop: continuous batching of independent contact solves on one GPU.
 //
-// Requests (grid, material, gap profile, solve parameters) enter a FIFO
-// queue.  n_slots worker threads, each with its own non-blocking HIP stream
-// (default priority), take the queue head as soon as a slot is free and the
-// device-memory budget admits it, so solves of different sizes, k and
-// indenters run concurrently on the GPU and new requests start while others
-// are still running.  Influence operators are cached by
-// (nx, ny, dx, dy, k, nu, E0, c0) together with pooled solver states;
-// entries that no running solve uses are evicted least-recently-used when
-// the budget requires.  Admission uses the footprint model of
-// bem_footprint(); a request that can never fit is rejected at submit.
+// Requests (grid, material, gap profile, solve parameters) are admitted as
+// device memory frees up (footprint model of bem_footprint(); influence
+// operators cached by (nx, ny, dx, dy, k, nu, E0, c0) with pooled solver
+// states, idle entries evicted least-recently-used) and run on the GPU
+// together, new requests starting while others are still in progress.
+//
+//  * Batched path: requests whose padded geometry the LDS Stockham sweeps
+//    cover (nx, ny <= 1024, displacement control) join the runner of their
+//    class (Lx, Ly, precision).  A runner owns up to batch_slots slots; each
+//    CG kernel is one launch over all slots of the class (batch.h), so small
+//    grids share launches instead of each paying its own.  Between chunks of
+//    iterations the runner retires converged slots (final sums, outputs),
+//    takes the next queued request of its class into a free slot, and steps
+//    each adhesive slot through its preload and detach / re-solve rounds.
+//  * Per-request path: every other request (larger grids, load control) is
+//    a bem_solve of its own on one of n_slots worker threads, each with its
+//    own non-blocking stream.
+//
+// Each request is solved from a cold start with the same kernels in the same
+// order as bem_solve, so its result does not depend on what else runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -21,10 +32,12 @@
 #include <mutex>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/bem.h"
+#include "cg_api.h"
 #include "internal.h"
 
 using namespace bem;
@@ -67,9 +80,18 @@ struct Req {
 
 }  // namespace
 
+namespace {
+struct Runner;
+using ClassKey = std::tuple<int, int, int>;   // Lx, Ly, precision
+}  // namespace
+
 struct bem_server_s {
   long long budget = 0;
   int n_slots = 0;
+  int batch_slots = 0;
+  std::map<ClassKey, Runner*> runners;
+  long long batched = 0;             // requests completed on the batched path
+  double slot_chunks = 0, chunks = 0; // occupancy: active slots summed over chunks
   int device = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -154,6 +176,422 @@ Entry* admit(bem_server_s* S, Req* r) {
   return e;
 }
 
+// Bookkeeping of a finished request (lock held): the state returns to its
+// entry's pool, statistics, wake the poller and the admission loops.
+void complete_locked(bem_server_s* S, Req* r, Entry* e, bem_state_t state, int rc) {
+  if (e) {
+    if (state) e->free_states[r->r.prm.precision].push_back(state);
+    e->in_use--;
+    e->last_use = ++S->tick;
+    if (!e->K && !e->building && e->in_use == 0) {  // failed build: drop the entry once unused
+      S->cache.erase(e->key);
+      S->used -= e->bytes;
+      free_entry(e);
+      delete e;
+    }
+  }
+  r->rc = rc;
+  r->t_end = Clock::now();
+  r->done = true;
+  S->running--;
+  if (rc >= 0) {
+    S->completed++;
+    S->latency.push_back(secs(r->t_submit, r->t_end));
+    S->wait.push_back(secs(r->t_submit, r->t_start));
+    S->t_last_end = r->t_end;
+  } else {
+    S->failed++;
+  }
+  r->h.clear();
+  r->h.shrink_to_fit();
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+}
+
+// Influence operator of an admitted request's entry: built here when the
+// request created the entry, else waited for.  Returns BEM_OK or an error.
+int entry_influence(bem_server_s* S, Req* r, Entry* e) {
+  if (r->builder) {
+    bem_influence_t K = nullptr;
+    const bem_request& q = r->r;
+    const int rc = bem_influence_ex(q.nx, q.ny, q.dx, q.dy, q.k, q.nu, q.E0, q.c0, &K);
+    std::unique_lock<std::mutex> lk(S->mu);
+    e->K = K;
+    e->building = false;
+    S->cv_done.notify_all();
+    return rc;
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_done.wait(lk, [&] { return !e->building; });
+  return e->K ? BEM_OK : BEM_EDEVICE;
+}
+
+// ---- batched path -------------------------------------------------------------
+
+// Phases of a slot between chunks.
+enum Phase {
+  PH_FREE,
+  PH_CG,          // a CG solve runs in the batch (mode DISP or FIXED)
+  PH_FIN_DISP,    // final sums of the non-adhesive solve queued
+  PH_DETACH,      // detachment of the fixed-set solve queued
+  PH_FIN_FIXED,   // final sums of the adhesive step queued
+  PH_OUT          // output copies queued
+};
+
+struct Slot {
+  Req* r = nullptr;
+  Entry* e = nullptr;
+  bem_state_t st = nullptr;
+  Phase ph = PH_FREE;
+  int mode = BATCH_EMPTY, it0 = 0;
+  bool adhesive = false;
+  double pcrit = 0.0, tol = 0.0, resid = 0.0;
+  int max_iter = 0, stall_limit = 0;
+  int status = BEM_OK, iters = 0, rounds = 0;
+};
+
+struct Runner {
+  bem_server_s* S = nullptr;
+  int Lx = 0, Ly = 0, prec = 0, nslots = 0;
+  std::deque<Req*> queue;         // this class's requests (server lock)
+  hipStream_t stream = nullptr;
+  CgScal* sc_dev = nullptr;       // one scalar block per slot
+  CgScal* sc_host = nullptr;      // pinned mirror
+  void* tab_dev = nullptr;        // BatchSlot<T>[nslots]
+  void* tab_host = nullptr;       // pinned
+  std::vector<Slot> slot;
+  std::thread th;
+};
+
+void runner_release(Runner* R) {
+  if (R->stream) hipStreamDestroy(R->stream);
+  if (R->sc_dev) hipFree(R->sc_dev);
+  if (R->tab_dev) hipFree(R->tab_dev);
+  if (R->sc_host) hipHostFree(R->sc_host);
+  if (R->tab_host) hipHostFree(R->tab_host);
+}
+
+int runner_alloc(Runner* R) {
+  hipError_t e = hipStreamCreateWithFlags(&R->stream, hipStreamNonBlocking);
+  const size_t tb = (size_t)R->nslots * std::max(sizeof(BatchSlot<float>), sizeof(BatchSlot<double>));
+  if (e == hipSuccess) e = hipMalloc((void**)&R->sc_dev, R->nslots * sizeof(CgScal));
+  if (e == hipSuccess) e = hipMalloc(&R->tab_dev, tb);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&R->sc_host, R->nslots * sizeof(CgScal), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&R->tab_host, tb, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(R->sc_dev, 0, R->nslots * sizeof(CgScal), R->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(R->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch runner");
+  R->slot.assign(R->nslots, Slot());
+  return BEM_OK;
+}
+
+template <typename T>
+CgBufs<T> slot_bufs(Runner* R, int i) {
+  bem_state_s* st = R->slot[i].st;
+  return {(T*)st->p, (T*)st->t, (T*)st->g, (T*)st->hd, st->mask, (cplx<T>*)st->S, st->part,
+          R->sc_dev + i};
+}
+
+// Scalars of a new CG solve of slot i (the bem_solve sequence: tolerances
+// into a cleared block, then the prepare kernel).
+template <typename T>
+hipError_t slot_start_cg(Runner* R, int i, int mode) {
+  Slot& sl = R->slot[i];
+  CgScal* h = R->sc_host + i;
+  std::memset(h, 0, sizeof(CgScal));
+  h->tol = sl.tol;
+  h->max_iter = sl.max_iter;
+  h->stall_limit = sl.stall_limit;
+  hipError_t e = hipMemcpyAsync(R->sc_dev + i, h, sizeof(CgScal), hipMemcpyHostToDevice, R->stream);
+  if (e == hipSuccess)
+    e = launch_prepare<T>((T*)sl.st->t, (T*)sl.st->p, sl.st->mask, mode == CG_FIXED, sl.st->n,
+                          R->stream);
+  sl.mode = mode;
+  sl.it0 = 0;
+  sl.ph = PH_CG;
+  return e;
+}
+
+// Set up an admitted request in slot i: influence, state, gap profile, cold
+// start and the first CG solve.  Returns < 0 to fail the request.
+template <typename T>
+int slot_setup(Runner* R, int i) {
+  Slot& sl = R->slot[i];
+  Req* r = sl.r;
+  int rc = entry_influence(R->S, r, sl.e);
+  if (rc) return rc;
+  bem_influence_s* K = sl.e->K;
+  rc = check_params(K, &r->r.prm, &sl.adhesive, &sl.pcrit);
+  if (rc) return rc;
+  for (double v : r->h)
+    if (!is_finite(v)) return set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
+  if (!sl.st && (rc = bem_state_create(K, &sl.st))) return rc;
+  bem_state_reset(sl.st);
+  if ((rc = ensure_precision(sl.st, R->prec, R->stream))) return rc;
+  const bem_params& P = r->r.prm;
+  sl.tol = P.tol > 0 ? P.tol : (P.precision == BEM_FP64 ? 1e-12 : 1e-6);
+  sl.max_iter = P.max_iter > 0 ? P.max_iter : 20000;
+  sl.stall_limit = P.stall_limit > 0 ? P.stall_limit
+                                     : (P.stall_limit < 0 ? 0 : (P.precision == BEM_MIXED ? 50 : 0));
+  sl.status = BEM_OK;
+  sl.iters = sl.rounds = 0;
+  sl.resid = 0.0;
+  bem_state_s* st = sl.st;
+  hipError_t e = hipMemcpyAsync(st->h64, r->h.data(), st->n * sizeof(double),
+                                hipMemcpyHostToDevice, R->stream);
+  // a cold adhesive solve first makes its contact set non-adhesively at
+  // max(d, d_preload) (Section 3.1)
+  const double d0 = sl.adhesive ? std::max(P.d, P.d_preload) : P.d;
+  if (e == hipSuccess) e = launch_make_hd<T>(st->h64, d0, (T*)st->hd, st->n, R->stream);
+  if (e == hipSuccess)
+    e = launch_cold_start<T>((T*)st->p, (const T*)st->hd, 1.0 / (K->C * K->K00), st->n, R->stream);
+  if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_DISP);
+  if (e != hipSuccess) return hip_fail(e, "batched solve setup");
+  return BEM_OK;
+}
+
+// Results and output copies of a finished slot (final sums in sc_host).
+template <typename T>
+hipError_t slot_outputs(Runner* R, int i) {
+  Slot& sl = R->slot[i];
+  Req* r = sl.r;
+  bem_state_s* st = sl.st;
+  const bem_influence_s* K = sl.e->K;
+  const CgScal* h = R->sc_host + i;
+  bem_result& res = r->res;
+  res.d = r->r.prm.d;
+  res.F = K->dx * K->dy * h->fin_sum_p;
+  res.n_contact = (long long)h->fin_contact;
+  res.area = (double)res.n_contact * K->dx * K->dy;
+  res.n_penetrating = sl.adhesive ? (long long)h->fin_pen : 0;
+  res.residual = sl.resid;
+  res.p_crit = sl.adhesive ? sl.pcrit : 0.0;
+  res.iters = sl.iters;
+  res.detach_rounds = sl.rounds;
+  res.status = sl.status;
+  hipError_t e = hipSuccess;
+  const size_t n = st->n;
+  if (r->r.p_out) {
+    const void* src = st->p;
+    if (!std::is_same<T, double>::value) {
+      e = launch_to_f64<T>((const T*)st->p, st->out64, n, R->stream);
+      src = st->out64;
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r->r.p_out, src, n * sizeof(double), hipMemcpyDeviceToHost, R->stream);
+  }
+  if (e == hipSuccess && r->r.contact_out)
+    e = hipMemcpyAsync(r->r.contact_out, st->mask, n, hipMemcpyDeviceToHost, R->stream);
+  sl.ph = PH_OUT;
+  return e;
+}
+
+// After a chunk (scalars in sc_host): the next step of every slot.  Each
+// step queues its kernels on the runner's stream; they complete before the
+// next chunk's scalars are read.  Returns a HIP error, if any.
+template <typename T>
+hipError_t slot_advance(Runner* R, int i, int chunk, std::vector<std::pair<int, int>>& finished) {
+  Slot& sl = R->slot[i];
+  const CgScal* h = R->sc_host + i;
+  hipError_t e = hipSuccess;
+  switch (sl.ph) {
+    case PH_CG:
+      if (!h->done) {
+        sl.it0 += chunk;
+        if (sl.it0 > sl.max_iter + 256) {   // the device stops itself at max_iter
+          set_error(BEM_EDEVICE, "batched CG loop did not report completion");
+          finished.push_back({i, BEM_EDEVICE});
+        }
+        break;
+      }
+      sl.iters += h->iter;
+      sl.resid = h->rhs2 > 0 ? std::sqrt(h->G / h->rhs2) : std::sqrt(h->G);
+      {
+        const int st = status_code(h->status);
+        if (st < 0) {   // as bem_solve: a non-finite solve returns at once
+          finished.push_back({i, st});
+          break;
+        }
+        sl.status = worse(sl.status, st);
+      }
+      if (sl.mode == CG_DISP) {
+        e = launch_finalize<T>(slot_bufs<T>(R, i), CG_DISP, sl.st->n, R->stream);
+        sl.ph = PH_FIN_DISP;
+      } else {
+        e = launch_detach<T>(slot_bufs<T>(R, i), sl.pcrit, sl.st->n, R->stream);
+        sl.ph = PH_DETACH;
+      }
+      sl.mode = BATCH_EMPTY;
+      break;
+    case PH_FIN_DISP:
+      if (sl.adhesive) {
+        // the pull-off step: fixed-set solves at d on the preload's contact set
+        e = launch_make_hd<T>(sl.st->h64, sl.r->r.prm.d, (T*)sl.st->hd, sl.st->n, R->stream);
+        if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_FIXED);
+      } else {
+        e = slot_outputs<T>(R, i);
+      }
+      break;
+    case PH_DETACH:
+      if (h->fin_detach == 0.0) {
+        e = launch_finalize<T>(slot_bufs<T>(R, i), CG_FIXED, sl.st->n, R->stream);
+        sl.ph = PH_FIN_FIXED;
+      } else {
+        ++sl.rounds;
+        if (sl.iters >= sl.max_iter * 8) {
+          sl.status = worse(sl.status, BEM_ENOCONV);
+          e = launch_finalize<T>(slot_bufs<T>(R, i), CG_FIXED, sl.st->n, R->stream);
+          sl.ph = PH_FIN_FIXED;
+        } else {
+          e = slot_start_cg<T>(R, i, CG_FIXED);
+        }
+      }
+      break;
+    case PH_FIN_FIXED:
+      e = slot_outputs<T>(R, i);
+      break;
+    case PH_OUT:
+      finished.push_back({i, sl.status});
+      break;
+    case PH_FREE:
+      break;
+  }
+  return e;
+}
+
+template <typename T>
+void runner_loop(Runner* R) {
+  bem_server_s* S = R->S;
+  (void)hipSetDevice(S->device);
+  constexpr int kChunk = 8;
+  std::vector<std::pair<int, int>> finished;
+  std::vector<int> fresh;
+  for (;;) {
+    // admission: queued requests of this class into free slots
+    fresh.clear();
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (;;) {
+        int active = 0;
+        for (const Slot& sl : R->slot) active += sl.ph != PH_FREE;
+        if (!S->stop) {
+          for (int i = 0; i < R->nslots && !R->queue.empty(); ++i) {
+            if (R->slot[i].ph != PH_FREE || R->slot[i].r) continue;
+            Entry* e = admit(S, R->queue.front());
+            if (!e) break;
+            Req* r = R->queue.front();
+            R->queue.pop_front();
+            r->t_start = Clock::now();
+            S->running++;
+            S->peak_running = std::max(S->peak_running, S->running);
+            Slot& sl = R->slot[i];
+            sl.r = r;
+            sl.e = e;
+            sl.st = r->lent;
+            fresh.push_back(i);
+            ++active;
+          }
+        }
+        if (active > 0) break;
+        if (S->stop) return;
+        S->cv_work.wait(lk);
+      }
+    }
+    // requests that build their influence operator first: a runner never
+    // waits for another thread's build before finishing its own, so two
+    // runners cannot wait on each other
+    std::stable_partition(fresh.begin(), fresh.end(), [&](int i) { return R->slot[i].r->builder; });
+    for (int i : fresh) {
+      const int rc = slot_setup<T>(R, i);
+      if (rc < 0) {   // out of the chunk; retired below
+        R->slot[i].ph = PH_FREE;
+        R->slot[i].mode = BATCH_EMPTY;
+        finished.push_back({i, rc});
+      }
+    }
+    // one chunk of iterations over the slots in a CG solve
+    auto* tab = (BatchSlot<T>*)R->tab_host;
+    unsigned modes = 0;
+    int ncg = 0, last = -1, any = -1;
+    for (int i = 0; i < R->nslots; ++i) {
+      Slot& sl = R->slot[i];
+      BatchSlot<T>& b = tab[i];
+      b = BatchSlot<T>{};
+      b.mode = BATCH_EMPTY;
+      if (sl.ph == PH_CG && sl.mode != BATCH_EMPTY) {
+        const CgBufs<T> bb = slot_bufs<T>(R, i);
+        b = BatchSlot<T>{bb.p, bb.t, bb.g, bb.hd, bb.mask, bb.S, bb.part, bb.sc,
+                         spec_view<T>(sl.e->K).KT, sl.e->K->nx, sl.e->K->ny, sl.it0, sl.mode};
+        modes |= 1u << sl.mode;
+        ++ncg;
+        last = i;
+        any = i;
+      }
+    }
+    hipError_t e = hipSuccess;
+    if (ncg > 0) {
+      const int used = last + 1;
+      e = hipMemcpyAsync(R->tab_dev, tab, used * sizeof(BatchSlot<T>), hipMemcpyHostToDevice,
+                         R->stream);
+      if (e == hipSuccess)
+        e = launch_batch_iterations<T>(R->slot[any].e->K->g, spec_view<T>(R->slot[any].e->K),
+                                       (const BatchSlot<T>*)R->tab_dev, used, modes, kChunk,
+                                       R->stream);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(R->sc_host, R->sc_dev, R->nslots * sizeof(CgScal), hipMemcpyDeviceToHost,
+                         R->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(R->stream);
+    if (ncg > 0) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->chunks += 1;
+      S->slot_chunks += ncg;
+    }
+    for (int i = 0; i < R->nslots && e == hipSuccess; ++i) {
+      bool done_already = false;
+      for (auto& f : finished) done_already |= f.first == i;
+      if (!done_already && R->slot[i].r) e = slot_advance<T>(R, i, kChunk, finished);
+    }
+    if (e != hipSuccess) {   // the stream is unusable: fail every active request
+      hip_fail(e, "batched solve");
+      for (int i = 0; i < R->nslots; ++i)
+        if (R->slot[i].r) finished.push_back({i, BEM_EDEVICE});
+      (void)hipStreamSynchronize(R->stream);
+    }
+    // retire finished slots
+    if (!finished.empty()) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (auto& f : finished) {
+        Slot& sl = R->slot[f.first];
+        if (!sl.r) continue;
+        if (f.second >= 0) S->batched++;
+        complete_locked(S, sl.r, sl.e, sl.st, f.second);
+        sl = Slot();
+      }
+      finished.clear();
+    }
+  }
+}
+
+void runner_main(Runner* R) {
+  if (R->prec == BEM_FP64)
+    runner_loop<double>(R);
+  else
+    runner_loop<float>(R);
+}
+
+// The class of a request on the batched path, or false for the per-request path.
+bool batch_class(const bem_server_s* S, const bem_request& q, ClassKey* key) {
+  if (S->batch_slots <= 0 || q.prm.control != BEM_CTRL_INDENT) return false;
+  int Mx = 2 * kMinL, My = 2 * kMinL;
+  while (Mx < 2 * q.nx) Mx <<= 1;
+  while (My < 2 * q.ny) My <<= 1;
+  Geom g{q.nx, q.ny, Mx / 2, My / 2, 0};
+  if (!batch_geometry(g)) return false;
+  *key = ClassKey{g.Lx, g.Ly, q.prm.precision};
+  return true;
+}
+
 void worker(bem_server_s* S, int slot) {
   (void)hipSetDevice(S->device);
   hipStream_t st = S->streams[slot];
@@ -179,20 +617,7 @@ void worker(bem_server_s* S, int slot) {
       S->peak_running = std::max(S->peak_running, S->running);
     }
     // build the influence operator if this request created the entry
-    int rc = BEM_OK;
-    if (r->builder) {
-      bem_influence_t K = nullptr;
-      const bem_request& q = r->r;
-      rc = bem_influence_ex(q.nx, q.ny, q.dx, q.dy, q.k, q.nu, q.E0, q.c0, &K);
-      std::unique_lock<std::mutex> lk(S->mu);
-      e->K = K;
-      e->building = false;
-      S->cv_done.notify_all();
-    } else {
-      std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_done.wait(lk, [&] { return !e->building; });
-      if (!e->K) rc = BEM_EDEVICE;
-    }
+    int rc = entry_influence(S, r, e);
     bem_state_t state = r->lent;
     if (rc == BEM_OK && !state) rc = bem_state_create(e->K, &state);
     if (rc == BEM_OK) {
@@ -201,34 +626,8 @@ void worker(bem_server_s* S, int slot) {
       rc = bem_solve(e->K, r->h.data(), &r->r.prm, state, r->r.p_out, r->r.contact_out, nullptr,
                      &r->res, st);
     }
-    {
-      std::unique_lock<std::mutex> lk(S->mu);
-      if (state) e->free_states[r->r.prm.precision].push_back(state);
-      e->in_use--;
-      e->last_use = ++S->tick;
-      if (!e->K && e->in_use == 0) {  // failed build: drop the entry once unused
-        S->cache.erase(e->key);
-        S->used -= e->bytes;
-        free_entry(e);
-        delete e;
-      }
-      r->rc = rc;
-      r->t_end = Clock::now();
-      r->done = true;
-      S->running--;
-      if (rc >= 0) {
-        S->completed++;
-        S->latency.push_back(secs(r->t_submit, r->t_end));
-        S->wait.push_back(secs(r->t_submit, r->t_start));
-        S->t_last_end = r->t_end;
-      } else {
-        S->failed++;
-      }
-      r->h.clear();
-      r->h.shrink_to_fit();
-      S->cv_done.notify_all();
-      S->cv_work.notify_all();
-    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    complete_locked(S, r, e, state, rc);
   }
 }
 
@@ -255,8 +654,11 @@ int bem_footprint(int nx, int ny, int precision, long long* influence_bytes,
   const long long Lx = Mx / 2, Ly = My / 2;
   const long long kpitch = ((Ly + 1) + 63) / 64 * 64;
   const long long n = (long long)nx * ny;
+  // coefficients, spectrum (FP64 + FP32), twiddles and the FP64 spectrum
+  // scratch the handle keeps from its build
   if (influence_bytes)
-    *influence_bytes = n * 8 + (Lx + 1) * kpitch * 12 + (long long)(Mx + My + Ly + Lx) * 24;
+    *influence_bytes = n * 8 + (Lx + 1) * kpitch * 12 + (long long)(Mx + My + Ly + Lx) * 24 +
+                       (long long)ny * Lx * 16;
   const long long ts = precision == BEM_FP64 ? 8 : 4;
   if (state_bytes)
     *state_bytes = n * (1 + 8 + 8) + state_partial_bytes() + 512 + 4 * n * ts +
@@ -265,12 +667,19 @@ int bem_footprint(int nx, int ny, int precision, long long* influence_bytes,
 }
 
 int bem_server_create(long long budget_bytes, int n_slots, bem_server_t* out) {
+  return bem_server_create_ex(budget_bytes, n_slots, 16, out);
+}
+
+int bem_server_create_ex(long long budget_bytes, int n_slots, int batch_slots, bem_server_t* out) {
   clear_error();
-  if (!out || budget_bytes <= 0 || n_slots < 1 || n_slots > 16)
-    return set_error(BEM_EINVAL, "bem_server_create: budget > 0, 1 <= n_slots <= 16");
+  if (!out || budget_bytes <= 0 || n_slots < 1 || n_slots > 16 || batch_slots < 0 ||
+      batch_slots > 64)
+    return set_error(BEM_EINVAL,
+                     "bem_server_create: budget > 0, 1 <= n_slots <= 16, 0 <= batch_slots <= 64");
   auto* S = new bem_server_s();
   S->budget = budget_bytes;
   S->n_slots = n_slots;
+  S->batch_slots = batch_slots;
   (void)hipGetDevice(&S->device);
   S->t0 = Clock::now();
   for (int i = 0; i < n_slots; ++i) {
@@ -309,6 +718,44 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
     return set_error(BEM_ENOMEM, "bem_server_submit: request needs %lld bytes, budget %lld",
                      fi + fs, S->budget);
   }
+  // the batched path: the runner of the request's class (made on first use)
+  ClassKey key;
+  Runner* R = nullptr;
+  if (batch_class(S, q, &key)) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      auto it = S->runners.find(key);
+      if (it != S->runners.end()) R = it->second;
+    }
+    if (!R) {
+      auto* nr = new Runner();
+      nr->S = S;
+      nr->Lx = std::get<0>(key);
+      nr->Ly = std::get<1>(key);
+      nr->prec = std::get<2>(key);
+      nr->nslots = S->batch_slots;
+      const int rc = runner_alloc(nr);
+      if (rc) {
+        runner_release(nr);
+        delete nr;
+        delete r;
+        return rc;
+      }
+      std::unique_lock<std::mutex> lk(S->mu);
+      auto it = S->runners.find(key);
+      if (it != S->runners.end()) {   // another submit made it meanwhile
+        lk.unlock();
+        runner_release(nr);
+        delete nr;
+        lk.lock();
+        R = S->runners.find(key)->second;
+      } else {
+        S->runners[key] = nr;
+        R = nr;
+        nr->th = std::thread(runner_main, nr);
+      }
+    }
+  }
   std::unique_lock<std::mutex> lk(S->mu);
   r->id = S->next_id++;
   r->t_submit = Clock::now();
@@ -317,9 +764,12 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
     S->t_first_submit = r->t_submit;
   }
   S->reqs[r->id] = r;
-  S->queue.push_back(r);
+  if (R)
+    R->queue.push_back(r);
+  else
+    S->queue.push_back(r);
   *id = r->id;
-  S->cv_work.notify_one();
+  S->cv_work.notify_all();
   return BEM_OK;
 }
 
@@ -349,6 +799,9 @@ int bem_server_stats(bem_server_t S, bem_server_stats_t* out) {
   out->completed = S->completed;
   out->failed = S->failed;
   out->queued = (long long)S->queue.size();
+  for (auto& kv : S->runners) out->queued += (long long)kv.second->queue.size();
+  out->batched = S->batched;
+  out->mean_batch_slots = S->chunks > 0 ? S->slot_chunks / S->chunks : 0.0;
   out->running = S->running;
   out->peak_running = S->peak_running;
   out->p50_latency_s = quantile(S->latency, 0.50);
@@ -377,6 +830,8 @@ int bem_server_reset_stats(bem_server_t S) {
   S->have_first = false;
   S->peak_running = S->running;
   S->cache_hits = S->cache_misses = S->evictions = 0;
+  S->batched = 0;
+  S->chunks = S->slot_chunks = 0;
   return BEM_OK;
 }
 
@@ -389,6 +844,11 @@ int bem_server_free(bem_server_t S) {
     S->cv_done.notify_all();
   }
   for (auto& t : S->workers) t.join();
+  for (auto& kv : S->runners) {
+    kv.second->th.join();
+    runner_release(kv.second);
+    delete kv.second;
+  }
   for (auto& kv : S->cache) {
     free_entry(kv.second);
     delete kv.second;

@@ -17,34 +17,11 @@
 #include <vector>
 
 #include "../../include/bem.h"
-#include "cg_launch.h"
+#include "cg_api.h"
 #include "internal.h"
 
 using namespace bem;
 
-struct bem_state_s {
-  bem_influence_s* K = nullptr;
-  size_t n = 0;
-  int precision = -1;  // precision of the T buffers below (-1: none yet)
-  void* p = nullptr;
-  void* t = nullptr;
-  void* g = nullptr;
-  void* hd = nullptr;
-  void* S = nullptr;
-  uint8_t* mask = nullptr;
-  double* h64 = nullptr;
-  double* out64 = nullptr;
-  double* part = nullptr;
-  CgScal* sc = nullptr;
-  CgScal* sc_host = nullptr;  // pinned
-  bool has_p = false, has_mask = false, pending_import = false, import_mask = false;
-  // g = C K * p + h - g_d for the current p (set by a displacement-controlled
-  // solve; a sweep's next step at another d starts from it, same h)
-  bool g_valid = false;
-  double g_d = 0.0;
-  long long device_bytes = 0;
-  int last_iters[3] = {0, 0, 0};  // iterations of the previous CG solve, per mode
-};
 
 namespace {
 
@@ -77,8 +54,10 @@ void free_typed(bem_state_s* st) {
 
 size_t tsize(int precision) { return precision == BEM_FP64 ? sizeof(double) : sizeof(float); }
 
+}  // namespace
+
 // Make the T buffers match `precision`, carrying a warm-start pressure over.
-int ensure_precision(bem_state_s* st, int precision, hipStream_t s) {
+int bem::ensure_precision(bem_state_s* st, int precision, hipStream_t s) {
   if (st->precision == precision) return BEM_OK;
   hipError_t e;
   if (st->has_p && st->precision >= 0) {
@@ -103,6 +82,8 @@ int ensure_precision(bem_state_s* st, int precision, hipStream_t s) {
   return BEM_OK;
 }
 
+namespace {
+
 template <typename T>
 CgBufs<T> bufs(bem_state_s* st) {
   return {(T*)st->p, (T*)st->t, (T*)st->g, (T*)st->hd, st->mask, (cplx<T>*)st->S, st->part,
@@ -116,7 +97,9 @@ struct SolveCfg {
   double W = 0.0;  // load control: prescribed sum of p
 };
 
-int status_code(int st) {
+}  // namespace
+
+int bem::status_code(int st) {
   switch (st) {
     case CG_ST_NOCONV: return BEM_ENOCONV;
     case CG_ST_FLOOR: return BEM_EFLOOR;
@@ -124,6 +107,8 @@ int status_code(int st) {
     default: return BEM_OK;
   }
 }
+
+namespace {
 
 // Run one CG solve to convergence on the device.  Returns the status code;
 // *iters receives the iterations of this solve.
@@ -184,10 +169,14 @@ int finalize(bem_state_s* st, int mode, hipStream_t s) {
   return BEM_OK;
 }
 
-int worse(int a, int b) {
+}  // namespace
+
+int bem::worse(int a, int b) {
   if (a < 0 || b < 0) return std::min(a, b);
   return std::max(a, b);
 }
+
+namespace {
 
 // Apply an imported (or precision-converted) pressure / contact set.
 template <typename T>
@@ -409,7 +398,10 @@ double p_crit_eq24(double k, double nu, double gamma, double dx, double E0, doub
                    (alpha_kn(k, nu) * (1.0 - nu * nu) * c1 * std::pow(c0, k) * std::pow(dx, 1.0 - k)));
 }
 
-int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, double* pcrit) {
+}  // namespace
+
+int bem::check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive,
+                      double* pcrit) {
   if (!P) return set_error(BEM_EINVAL, "bem_solve: params is NULL");
   if (P->precision != BEM_FP64 && P->precision != BEM_MIXED)
     return set_error(BEM_EINVAL, "bem_solve: unknown precision %d", P->precision);
@@ -433,6 +425,8 @@ int check_params(const bem_influence_s* K, const bem_params* P, bool* adhesive, 
   }
   return BEM_OK;
 }
+
+namespace {
 
 int solve_common(bem_influence_t K, const double* h_dev, const bem_params* prm, bem_state_t state,
                  double* p_out, unsigned char* c_out, double* u_out, bool outs_host,

@@ -1,6 +1,16 @@
 """Driver of the serving loop (bem_server_*): submits a request stream with
 Poisson arrivals and collects latency / throughput.  Argument marshalling and
-timing only; every solve runs in the library."""
+timing only; every solve runs in the library.
+
+    python -m paper_1612_08395_amd.serving --requests 10000 --out stream.json
+
+runs the seeded request stream (inputs.serving_requests) at saturation for
+both precisions, then with Poisson arrivals at 0.8 x the FP64 saturation
+rate, and writes the statistics as JSON.
+"""
+import argparse
+import json
+import sys
 import time
 
 import numpy as np
@@ -9,16 +19,18 @@ from . import bem
 
 
 def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, seed=0,
-               nu=0.3):
+               nu=0.3, batch_slots=16, want_p=False, progress=None):
     """Submit `requests` (dicts from inputs.serving_requests) to a fresh server.
     qps None: all at once (saturation).  Otherwise Poisson arrivals at rate qps.
-    Returns a dict of statistics."""
-    srv = bem.bem_server_create(budget_bytes, n_slots)
+    batch_slots: solves per batched launch group (0: every request is a solve
+    of its own).  Returns a dict of statistics; with want_p also the list of
+    (status, result, pressure) per request under "results"."""
+    srv = bem.bem_server_create_ex(budget_bytes, n_slots, batch_slots)
     rng = np.random.default_rng(seed)
     ids = []
     t0 = time.perf_counter()
     t_next = t0
-    for r in requests:
+    for j, r in enumerate(requests):
         if qps is not None:
             t_next += rng.exponential(1.0 / qps)
             delay = t_next - time.perf_counter()
@@ -26,12 +38,69 @@ def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, s
                 time.sleep(delay)
         prm = bem.bem_params_init(d=r["d"], d_preload=r["d_preload"], gamma=r["gamma"],
                                   precision=precision)
-        ids.append(srv.submit(r["n"], r["n"], 1.0 / r["n"], r["k"], nu, r["h"], prm))
-    statuses = [srv.poll(i)[0] for i in ids]
+        ids.append(srv.submit(r["n"], r["n"], 1.0 / r["n"], r["k"], nu, r["h"], prm,
+                              want_p=want_p))
+        if progress and (j + 1) % progress == 0:
+            print(f"[serving] submitted {j + 1}/{len(requests)}", file=sys.stderr, flush=True)
+    polled = [srv.poll(i) for i in ids]
     t1 = time.perf_counter()
     st = srv.stats().as_dict()
     srv.free()
+    statuses = [p[0] for p in polled]
     st["wall_s"] = t1 - t0
     st["offered_qps"] = qps
     st["status_counts"] = {int(s): statuses.count(s) for s in set(statuses)}
+    if want_p:
+        st["results"] = [(p[0], p[1], p[2], p[3]) for p in polled]
     return st
+
+
+KEYS_SAT = ("solves_per_s", "p50_latency_s", "p99_latency_s", "mean_wait_s", "peak_running",
+            "batched", "mean_batch_slots", "cache_hits", "cache_misses", "evictions",
+            "status_counts", "wall_s")
+KEYS_POISSON = ("offered_qps", "solves_per_s", "p50_latency_s", "p99_latency_s", "mean_wait_s",
+                "peak_running", "batched", "mean_batch_slots", "status_counts", "wall_s")
+
+
+def main():
+    from . import inputs
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--batch-slots", type=int, default=16)
+    ap.add_argument("--budget-gb", type=float, default=8.0)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    reqs = inputs.serving_requests(a.requests, a.seed)
+    print(f"[serving] {len(reqs)} requests built", file=sys.stderr, flush=True)
+    budget = int(a.budget_gb * (1 << 30))
+    out = {"requests": a.requests, "seed": a.seed, "slots": a.slots,
+           "batch_slots": a.batch_slots, "budget_bytes": budget}
+    sat = {}
+    for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        s = run_stream(reqs, prec, None, a.slots, budget, batch_slots=a.batch_slots,
+                       progress=1000)
+        sat[name] = s["solves_per_s"]
+        out[f"{name}_saturation"] = {k: s[k] for k in KEYS_SAT}
+        print(f"[serving] {name} saturation {s['solves_per_s']:.1f} solves/s", file=sys.stderr,
+              flush=True)
+    qps = 0.8 * sat["fp64"]
+    for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        s = run_stream(reqs, prec, qps, a.slots, budget, seed=7, batch_slots=a.batch_slots,
+                       progress=1000)
+        out[f"{name}_poisson"] = {k: s[k] for k in KEYS_POISSON}
+        print(f"[serving] {name} poisson p99 {s['p99_latency_s']:.3f} s", file=sys.stderr,
+              flush=True)
+    line = json.dumps(out)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(line + "\n")
+    print(line, flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -37,20 +37,16 @@ def _mix(bem, rng, count):
     return reqs
 
 
-def test_alone_and_in_the_mix_are_identical():
-    from paper_1612_08395_amd import bem
-    announce("server-mix")
-    rng = np.random.default_rng(5)
-    reqs = _mix(bem, rng, 24)
-    srv = bem.bem_server_create(budget_bytes=4 << 30, n_slots=4)
+def _alone_vs_mix(bem, reqs, batch_slots, extra=()):
+    srv = bem.bem_server_create_ex(budget_bytes=4 << 30, n_slots=4, batch_slots=batch_slots)
     ids = [srv.submit(n, n, 1.0 / n, k, 0.3, h, prm, want_p=True) for (n, k, h, prm) in reqs]
     got = [srv.poll(i) for i in ids]
     st = srv.stats()
+    srv.free()
     assert st.completed == len(reqs) and st.failed == 0
     assert st.peak_running >= 2                 # requests overlapped on the device
     assert st.device_bytes_reserved <= 4 << 30  # both precisions share the pools
     assert st.p99_latency_s >= st.p50_latency_s > 0
-    srv.free()
     for (n, k, h, prm), (status, res, p, c) in zip(reqs, got):
         K = bem.bem_influence(n, n, 1.0 / n, k, 0.3)
         rc, ra, pa, ca, _ = bem.bem_solve(K, h, prm)
@@ -59,6 +55,99 @@ def test_alone_and_in_the_mix_are_identical():
         assert np.array_equal(p, pa)            # bitwise: deterministic reductions
         assert np.array_equal(c, ca)
         assert res.F == ra.F and res.iters == ra.iters
+        assert res.n_contact == ra.n_contact and res.detach_rounds == ra.detach_rounds
+        assert res.residual == ra.residual and res.n_penetrating == ra.n_penetrating
+    return st
+
+
+def test_alone_and_in_the_mix_are_identical():
+    # default server: every request here (48^2 ... 256^2, displacement
+    # control) runs on the batched path, its CG kernels sharing launches with
+    # the other requests of its geometry and precision
+    from paper_1612_08395_amd import bem
+    announce("server-mix batched")
+    rng = np.random.default_rng(5)
+    reqs = _mix(bem, rng, 24)
+    st = _alone_vs_mix(bem, reqs, 16)
+    assert st.batched == len(reqs)
+    assert st.mean_batch_slots > 1.0            # launches did carry several solves
+    print(f"[server-mix] mean solves per batched launch {st.mean_batch_slots:.2f}", flush=True)
+
+
+def test_alone_and_in_the_mix_per_request_path():
+    from paper_1612_08395_amd import bem
+    announce("server-mix per-request")
+    rng = np.random.default_rng(6)
+    reqs = _mix(bem, rng, 12)
+    st = _alone_vs_mix(bem, reqs, 0)
+    assert st.batched == 0
+
+
+def test_both_paths_together():
+    # a batched geometry class next to requests of the per-request path: a
+    # grid beyond the batched sweeps (1100 x 1100) and a load-controlled solve
+    from paper_1612_08395_amd import bem
+    announce("server both paths")
+    srv = bem.bem_server_create_ex(budget_bytes=4 << 30, n_slots=2, batch_slots=8)
+    reqs = []
+    for i, n in enumerate((64, 64, 96, 1100, 64)):
+        h = inputs.parabolic(n, 1.0, 1.0)
+        if i == 4:
+            prm = bem.bem_params_init(control=bem.BEM_CTRL_FORCE, F=2e-3)
+        else:
+            prm = bem.bem_params_init(d=0.01, precision=bem.BEM_MIXED if i % 2 else bem.BEM_FP64)
+        reqs.append((n, 0.2, h, prm))
+    ids = [srv.submit(n, n, 1.0 / n, k, 0.3, h, prm, want_p=True) for (n, k, h, prm) in reqs]
+    got = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    srv.free()
+    assert st.completed == len(reqs) and st.failed == 0
+    assert st.batched == 3
+    for (n, k, h, prm), (status, res, p, c) in zip(reqs, got):
+        K = bem.bem_influence(n, n, 1.0 / n, k, 0.3)
+        rc, ra, pa, ca, _ = bem.bem_solve(K, h, prm)
+        K.free()
+        assert status == rc and np.array_equal(p, pa) and np.array_equal(c, ca)
+        assert res.d == ra.d
+
+
+def test_served_results_match_oracle():
+    # a seeded sample of the serving stream (grids up to 128^2), served in
+    # both precisions, against the oracle: non-adhesive solves, and adhesive
+    # requests as the non-adhesive preload followed by the pull-off step
+    from oracle import influence as inf
+    from oracle import material as m
+    from oracle import solver as so
+    from oracle.convolution import FFTConvolver
+    from paper_1612_08395_amd import bem
+    from paper_1612_08395_amd.serving import run_stream
+    from tests.gpu_util import rel_l2
+    announce("served vs oracle")
+    reqs = [r for r in inputs.serving_requests(200, 2024) if r["n"] <= 128][:10]
+    assert len(reqs) == 10 and any(r["gamma"] > 0 for r in reqs)
+    out = {prec: run_stream(reqs, prec, None, want_p=True)["results"]
+           for prec in (bem.BEM_FP64, bem.BEM_MIXED)}
+    for j, r in enumerate(reqs):
+        n, k, nu = r["n"], r["k"], 0.3
+        dx = 1.0 / n
+        Kq = inf.influence_quarter(n, n, dx, dx, k)
+        C = m.compliance(k, nu)
+        conv = FFTConvolver(Kq, C)
+        if r["gamma"] > 0:
+            load = so.solve_nonadhesive(Kq, C, r["h"], max(r["d"], r["d_preload"]), conv=conv)
+            ref = so.adhesive_step(Kq, C, r["h"], r["d"], load.contact, load.p,
+                                   m.p_crit(k, nu, r["gamma"], dx), conv=conv)
+        else:
+            ref = so.solve_nonadhesive(Kq, C, r["h"], r["d"], conv=conv)
+        for prec, tol in ((bem.BEM_FP64, 1e-10), (bem.BEM_MIXED, 2e-5)):
+            status, res, p, c = out[prec][j]
+            print(f"[served {j}] n={n} k={k} {r['shape']} gamma={r['gamma']:.2e} prec={prec} "
+                  f"status {status} contact {int(c.sum())} vs {int(ref.contact.sum())}", flush=True)
+            assert status in (0, bem.BEM_EFLOOR)
+            nref = int(ref.contact.sum())
+            assert abs(int(c.sum()) - nref) <= max(1, 1e-3 * nref)
+            if np.array_equal(c.astype(bool), ref.contact) and np.abs(ref.p).max() > 0:
+                assert rel_l2(p, ref.p) <= tol
 
 
 def test_admission_under_a_tight_budget():
