@@ -209,8 +209,17 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
     t = time.perf_counter() - t0
     # sample_iters iterations plus one extra convolution at the final check
     per_iter = t / (sample_iters + 0.5)
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(1.0 / (per_iter * iters_per_solve), 5), "unit": "solves/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "cpu_model": cpu_model, "kind": "oracle",
             "sample": (f"{sample_iters} CG iterations of the FP64 oracle (numpy/scipy.fft, "
                        f"{cores} workers) at 2048^2, depth d10, {t:.1f} s; scaled by the GPU "
                        f"FP64 mean of {iters_per_solve:.1f} iterations/solve; influence "
@@ -421,26 +430,52 @@ def oracle_units(cores, Kq):
 
 def serving(count, slots, bem):
     """Request stream of mixed grids (64^2..1024^2), k, indenters, 50 %
-    adhesive: saturation throughput of each path, then Poisson arrivals at
-    0.8 x the FP64 saturation rate for both paths."""
+    adhesive (inputs.serving_requests): saturation throughput of each path
+    with continuous batching (16 slots per geometry class), then Poisson
+    arrivals at 0.8 x the FP64 saturation rate for both paths; the MIXED
+    saturation run once more without batching (every request a solve of its
+    own) for comparison; and the requests the MIXED path stopped at its
+    rounding floor (BEM_EFLOOR), solved alone in both precisions, with their
+    pressure difference."""
     from paper_1612_08395_amd import inputs
-    from paper_1612_08395_amd.serving import run_stream
+    from paper_1612_08395_amd.serving import KEYS_POISSON, KEYS_SAT, run_stream
     reqs = inputs.serving_requests(count, 2024)
-    out = {"requests": count, "slots": slots, "budget_bytes": 8 << 30}
+    out = {"requests": count, "slots": slots, "batch_slots": 16, "budget_bytes": 8 << 30}
     sat = {}
+    floor_idx = []
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
         s = run_stream(reqs, prec, None, slots)
         sat[name] = s["solves_per_s"]
-        out[f"{name}_saturation"] = {k: s[k] for k in ("solves_per_s", "p50_latency_s",
-                                                       "p99_latency_s", "peak_running",
-                                                       "cache_hits", "cache_misses", "evictions",
-                                                       "status_counts")}
+        out[f"{name}_saturation"] = {k: s[k] for k in KEYS_SAT}
+        if prec == bem.BEM_MIXED:
+            floor_idx = [j for j, st in enumerate(s["statuses"]) if st == bem.BEM_EFLOOR]
+    s = run_stream(reqs, bem.BEM_MIXED, None, slots, batch_slots=0)
+    out["mixed_saturation_unbatched"] = {k: s[k] for k in KEYS_SAT}
     qps = 0.8 * sat["fp64"]
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
         s = run_stream(reqs, prec, qps, slots, seed=7)
-        out[f"{name}_poisson"] = {k: s[k] for k in ("offered_qps", "solves_per_s", "p50_latency_s",
-                                                    "p99_latency_s", "mean_wait_s", "peak_running",
-                                                    "status_counts")}
+        out[f"{name}_poisson"] = {k: s[k] for k in KEYS_POISSON}
+    floors = []
+    for j in floor_idx:
+        r = reqs[j]
+        n = r["n"]
+        K = bem.bem_influence(n, n, 1.0 / n, r["k"], 0.3)
+        ps = {}
+        for prec in (bem.BEM_MIXED, bem.BEM_FP64):
+            prm = bem.bem_params_init(d=r["d"], d_preload=r["d_preload"], gamma=r["gamma"],
+                                      precision=prec)
+            _, res, p, c, _ = bem.bem_solve(K, r["h"], prm)
+            ps[prec] = (p, int(c.sum()), res)
+        K.free()
+        p32, c32, r32 = ps[bem.BEM_MIXED]
+        p64, c64, _ = ps[bem.BEM_FP64]
+        nrm = float(np.linalg.norm(p64))
+        floors.append({"n": n, "k": r["k"], "shape": r["shape"], "adhesive": r["gamma"] > 0,
+                       "residual_mixed": float(f"{r32.residual:.3e}"),
+                       "rel_l2_pressure_vs_fp64": float(f"{np.linalg.norm(p32 - p64) / nrm:.3e}")
+                       if nrm > 0 else 0.0,
+                       "contact_mixed": c32, "contact_fp64": c64})
+    out["mixed_floor_requests"] = floors
     return out
 
 

@@ -309,6 +309,9 @@ typedef struct {
   long long device_bytes_reserved, cache_entries, cache_hits, cache_misses, evictions;
   long long batched;                    /* completed on the batched path */
   double mean_batch_slots;              /* mean solves per batched launch chunk */
+  double engine_launch_s;               /* batched path's thread: queueing launches, */
+  double engine_sync_s;                 /* waiting for the GPU, */
+  double engine_step_s;                 /* stepping the solves between chunks (s) */
 } bem_server_stats_t;
 
 /*
@@ -318,7 +321,7 @@ typedef struct {
  * (idle cache entries are evicted least-recently-used) and runs on the GPU
  * together with the requests already in progress.
  *  - Batched path (batch_slots > 0): displacement-controlled requests with
- *    nx, ny <= 1024 are grouped by padded geometry and precision; each group
+ *    nx, ny <= 256 are grouped by padded geometry and precision; each group
  *    runs up to batch_slots solves whose conjugate-gradient kernels share
  *    launches (one launch per kernel for all of them), admitting queued
  *    requests as slots free up between chunks of iterations.

@@ -399,7 +399,9 @@ class ServerStats(ctypes.Structure):
                 ("device_bytes_reserved", ctypes.c_longlong),
                 ("cache_entries", ctypes.c_longlong), ("cache_hits", ctypes.c_longlong),
                 ("cache_misses", ctypes.c_longlong), ("evictions", ctypes.c_longlong),
-                ("batched", ctypes.c_longlong), ("mean_batch_slots", _c_double)]
+                ("batched", ctypes.c_longlong), ("mean_batch_slots", _c_double),
+                ("engine_launch_s", _c_double), ("engine_sync_s", _c_double),
+                ("engine_step_s", _c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -6,9 +6,8 @@
 // states, idle entries evicted least-recently-used) and run on the GPU
 // together, new requests starting while others are still in progress.
 //
-//  * Batched path: requests whose padded geometry the LDS Stockham sweeps
-//    cover (nx, ny <= 1024, displacement control) join the runner of their
-//    class (Lx, Ly, precision).  A runner owns up to batch_slots slots; each
+//  * Batched path: small requests (nx, ny <= 256, displacement control)
+//    join the runner of their class (Lx, Ly, precision).  A runner owns up to batch_slots slots; each
 //    CG kernel is one launch over all slots of the class (batch.h), so small
 //    grids share launches instead of each paying its own.  Between chunks of
 //    iterations the runner retires converged slots (final sums, outputs),
@@ -76,6 +75,7 @@ struct Req {
   long long need_infl = 0, need_state = 0;
   bem_state_t lent = nullptr;  // pooled state handed over at admission
   bool builder = false;        // this request created the cache entry
+  Entry* entry = nullptr;      // batched path: admitted entry (prepared by a worker)
 };
 
 }  // namespace
@@ -90,7 +90,11 @@ struct bem_server_s {
   int n_slots = 0;
   int batch_slots = 0;
   std::map<ClassKey, Runner*> runners;
+  std::vector<Runner*> runner_list;    // creation order (engine thread, under the lock)
+  std::thread engine;                  // the batched path's launch thread
+  std::vector<hipStream_t> engine_streams;
   long long batched = 0;             // requests completed on the batched path
+  double eng_launch = 0, eng_sync = 0, eng_step = 0;  // engine thread seconds
   double slot_chunks = 0, chunks = 0; // occupancy: active slots summed over chunks
   int device = 0;
   std::mutex mu;
@@ -254,17 +258,24 @@ struct Runner {
   bem_server_s* S = nullptr;
   int Lx = 0, Ly = 0, prec = 0, nslots = 0;
   std::deque<Req*> queue;         // this class's requests (server lock)
+  // prepared by the worker threads (influence built, state typed, gap
+  // profile on the device): the runner takes them into free slots
+  std::deque<Req*> ready;
+  int preparing = 0, active = 0;  // server lock
   hipStream_t stream = nullptr;
   CgScal* sc_dev = nullptr;       // one scalar block per slot
   CgScal* sc_host = nullptr;      // pinned mirror
   void* tab_dev = nullptr;        // BatchSlot<T>[nslots]
   void* tab_host = nullptr;       // pinned
   std::vector<Slot> slot;
-  std::thread th;
+  std::vector<int> fresh;         // slots filled at this round's admission
+  int last_chunk_slots = 0;       // slots in this round's chunk
+  hipEvent_t done_ev = nullptr;   // recorded after a round's launches
+  bool in_flight = false;         // a round is queued on the stream
 };
 
 void runner_release(Runner* R) {
-  if (R->stream) hipStreamDestroy(R->stream);
+  if (R->done_ev) hipEventDestroy(R->done_ev);
   if (R->sc_dev) hipFree(R->sc_dev);
   if (R->tab_dev) hipFree(R->tab_dev);
   if (R->sc_host) hipHostFree(R->sc_host);
@@ -272,7 +283,7 @@ void runner_release(Runner* R) {
 }
 
 int runner_alloc(Runner* R) {
-  hipError_t e = hipStreamCreateWithFlags(&R->stream, hipStreamNonBlocking);
+  hipError_t e = hipEventCreateWithFlags(&R->done_ev, hipEventDisableTiming);
   const size_t tb = (size_t)R->nslots * std::max(sizeof(BatchSlot<float>), sizeof(BatchSlot<double>));
   if (e == hipSuccess) e = hipMalloc((void**)&R->sc_dev, R->nslots * sizeof(CgScal));
   if (e == hipSuccess) e = hipMalloc(&R->tab_dev, tb);
@@ -312,22 +323,16 @@ hipError_t slot_start_cg(Runner* R, int i, int mode) {
   return e;
 }
 
-// Set up an admitted request in slot i: influence, state, gap profile, cold
-// start and the first CG solve.  Returns < 0 to fail the request.
+// Start a prepared request in slot i (influence, typed state and gap
+// profile on the device already): cold start and the first CG solve, the
+// bem_solve sequence.  Returns < 0 to fail the request.
 template <typename T>
 int slot_setup(Runner* R, int i) {
   Slot& sl = R->slot[i];
   Req* r = sl.r;
-  int rc = entry_influence(R->S, r, sl.e);
-  if (rc) return rc;
   bem_influence_s* K = sl.e->K;
-  rc = check_params(K, &r->r.prm, &sl.adhesive, &sl.pcrit);
+  int rc = check_params(K, &r->r.prm, &sl.adhesive, &sl.pcrit);
   if (rc) return rc;
-  for (double v : r->h)
-    if (!is_finite(v)) return set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
-  if (!sl.st && (rc = bem_state_create(K, &sl.st))) return rc;
-  bem_state_reset(sl.st);
-  if ((rc = ensure_precision(sl.st, R->prec, R->stream))) return rc;
   const bem_params& P = r->r.prm;
   sl.tol = P.tol > 0 ? P.tol : (P.precision == BEM_FP64 ? 1e-12 : 1e-6);
   sl.max_iter = P.max_iter > 0 ? P.max_iter : 20000;
@@ -337,17 +342,46 @@ int slot_setup(Runner* R, int i) {
   sl.iters = sl.rounds = 0;
   sl.resid = 0.0;
   bem_state_s* st = sl.st;
-  hipError_t e = hipMemcpyAsync(st->h64, r->h.data(), st->n * sizeof(double),
-                                hipMemcpyHostToDevice, R->stream);
   // a cold adhesive solve first makes its contact set non-adhesively at
   // max(d, d_preload) (Section 3.1)
   const double d0 = sl.adhesive ? std::max(P.d, P.d_preload) : P.d;
-  if (e == hipSuccess) e = launch_make_hd<T>(st->h64, d0, (T*)st->hd, st->n, R->stream);
+  hipError_t e = launch_make_hd<T>(st->h64, d0, (T*)st->hd, st->n, R->stream);
   if (e == hipSuccess)
     e = launch_cold_start<T>((T*)st->p, (const T*)st->hd, 1.0 / (K->C * K->K00), st->n, R->stream);
   if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_DISP);
   if (e != hipSuccess) return hip_fail(e, "batched solve setup");
   return BEM_OK;
+}
+
+// Worker-thread half of a batched request (outside the lock): influence
+// operator, a state typed for the precision, and the gap profile on the
+// device.  Then the request joins its runner's ready list, or fails.
+void prepare_batched(bem_server_s* S, Runner* R, Req* r, hipStream_t s) {
+  Entry* e = r->entry;
+  bem_state_t state = r->lent;
+  int rc = entry_influence(S, r, e);
+  for (double v : r->h)
+    if (rc == BEM_OK && !is_finite(v)) rc = set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
+  if (rc == BEM_OK && !state) rc = bem_state_create(e->K, &state);
+  if (rc == BEM_OK) {
+    bem_state_reset(state);
+    rc = ensure_precision(state, R->prec, s);
+  }
+  if (rc == BEM_OK) {
+    hipError_t he = hipMemcpyAsync(state->h64, r->h.data(), state->n * sizeof(double),
+                                   hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) rc = hip_fail(he, "gap profile upload");
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  R->preparing--;
+  if (rc == BEM_OK) {
+    r->lent = state;
+    R->ready.push_back(r);
+    S->cv_work.notify_all();
+  } else {
+    complete_locked(S, r, e, state, rc);
+  }
 }
 
 // Results and output copies of a finished slot (final sums in sc_host).
@@ -459,126 +493,187 @@ hipError_t slot_advance(Runner* R, int i, int chunk, std::vector<std::pair<int, 
   return e;
 }
 
+// One class's part of a round: start the solves admitted into its free
+// slots, queue one chunk of iterations over its slots in a CG solve, and
+// the copy of its scalar blocks, all on the class's stream.
 template <typename T>
-void runner_loop(Runner* R) {
-  bem_server_s* S = R->S;
+hipError_t class_launch(Runner* R, int chunk, std::vector<std::pair<int, int>>& finished) {
+  for (int i : R->fresh) {
+    const int rc = slot_setup<T>(R, i);
+    if (rc < 0) {   // out of the chunk; retired below
+      R->slot[i].ph = PH_FREE;
+      R->slot[i].mode = BATCH_EMPTY;
+      finished.push_back({i, rc});
+    }
+  }
+  auto* tab = (BatchSlot<T>*)R->tab_host;
+  unsigned modes = 0;
+  int ncg = 0, last = -1;
+  for (int i = 0; i < R->nslots; ++i) {
+    Slot& sl = R->slot[i];
+    BatchSlot<T>& b = tab[i];
+    b = BatchSlot<T>{};
+    b.mode = BATCH_EMPTY;
+    if (sl.ph == PH_CG && sl.mode != BATCH_EMPTY) {
+      const CgBufs<T> bb = slot_bufs<T>(R, i);
+      b = BatchSlot<T>{bb.p, bb.t, bb.g, bb.hd, bb.mask, bb.S, bb.part, bb.sc,
+                       spec_view<T>(sl.e->K).KT, sl.e->K->nx, sl.e->K->ny, sl.it0, sl.mode};
+      modes |= 1u << sl.mode;
+      ++ncg;
+      last = i;
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (ncg > 0) {
+    const int used = last + 1;
+    e = hipMemcpyAsync(R->tab_dev, tab, used * sizeof(BatchSlot<T>), hipMemcpyHostToDevice,
+                       R->stream);
+    if (e == hipSuccess)
+      e = launch_batch_iterations<T>(R->slot[last].e->K->g, spec_view<T>(R->slot[last].e->K),
+                                     (const BatchSlot<T>*)R->tab_dev, used, modes, chunk,
+                                     R->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(R->sc_host, R->sc_dev, R->nslots * sizeof(CgScal), hipMemcpyDeviceToHost,
+                       R->stream);
+  R->last_chunk_slots = ncg;
+  return e;
+}
+
+// After the round's synchronisation: the next step of each of the class's slots.
+template <typename T>
+hipError_t class_advance(Runner* R, int chunk, std::vector<std::pair<int, int>>& finished) {
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < R->nslots && e == hipSuccess; ++i) {
+    bool done_already = false;
+    for (auto& f : finished) done_already |= f.first == i;
+    if (!done_already && R->slot[i].r) e = slot_advance<T>(R, i, chunk, finished);
+  }
+  return e;
+}
+
+// The batched path's launch thread.  Each class advances on its own: when
+// its previous round has completed (event query), its slots take their next
+// step, finished requests are retired, prepared requests of the class fill
+// free slots, and its next round (setup of new slots, one chunk of
+// iterations, the copy of its scalar blocks) is queued on its stream.
+// Classes share the server's few engine streams round-robin (one per
+// hardware queue); no class waits for another's rounds.
+void engine_loop(bem_server_s* S) {
   (void)hipSetDevice(S->device);
   constexpr int kChunk = 8;
-  std::vector<std::pair<int, int>> finished;
-  std::vector<int> fresh;
+  std::vector<std::pair<int, int>> fin;
   for (;;) {
-    // admission: queued requests of this class into free slots
-    fresh.clear();
+    std::vector<Runner*> rs;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
-        int active = 0;
-        for (const Slot& sl : R->slot) active += sl.ph != PH_FREE;
-        if (!S->stop) {
-          for (int i = 0; i < R->nslots && !R->queue.empty(); ++i) {
-            if (R->slot[i].ph != PH_FREE || R->slot[i].r) continue;
-            Entry* e = admit(S, R->queue.front());
-            if (!e) break;
-            Req* r = R->queue.front();
-            R->queue.pop_front();
-            r->t_start = Clock::now();
-            S->running++;
-            S->peak_running = std::max(S->peak_running, S->running);
-            Slot& sl = R->slot[i];
-            sl.r = r;
-            sl.e = e;
-            sl.st = r->lent;
-            fresh.push_back(i);
-            ++active;
-          }
+        bool work = false;
+        int preparing = 0;
+        for (Runner* R : S->runner_list) {
+          preparing += R->preparing;
+          work |= R->in_flight || R->active > 0 || !R->ready.empty();
         }
-        if (active > 0) break;
-        if (S->stop) return;
+        if (work) break;
+        if (S->stop && preparing == 0) return;
         S->cv_work.wait(lk);
       }
+      rs = S->runner_list;
     }
-    // requests that build their influence operator first: a runner never
-    // waits for another thread's build before finishing its own, so two
-    // runners cannot wait on each other
-    std::stable_partition(fresh.begin(), fresh.end(), [&](int i) { return R->slot[i].r->builder; });
-    for (int i : fresh) {
-      const int rc = slot_setup<T>(R, i);
-      if (rc < 0) {   // out of the chunk; retired below
-        R->slot[i].ph = PH_FREE;
-        R->slot[i].mode = BATCH_EMPTY;
-        finished.push_back({i, rc});
+    bool progressed = false;
+    for (Runner* R : rs) {
+      // 1. a completed round: the next step of every slot, then retirement
+      if (R->in_flight) {
+        hipError_t e = hipEventQuery(R->done_ev);
+        if (e == hipErrorNotReady) continue;
+        R->in_flight = false;
+        progressed = true;
+        fin.clear();
+        const Clock::time_point t0 = Clock::now();
+        if (e == hipSuccess)
+          e = R->prec == BEM_FP64 ? class_advance<double>(R, kChunk, fin)
+                                  : class_advance<float>(R, kChunk, fin);
+        if (e != hipSuccess) {   // the stream is unusable: fail the class's requests
+          hip_fail(e, "batched solve");
+          for (int i = 0; i < R->nslots; ++i)
+            if (R->slot[i].r) fin.push_back({i, BEM_EDEVICE});
+          (void)hipStreamSynchronize(R->stream);
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->eng_step += secs(t0, Clock::now());
+        for (auto& f : fin) {
+          Slot& sl = R->slot[f.first];
+          if (!sl.r) continue;
+          if (f.second >= 0) S->batched++;
+          complete_locked(S, sl.r, sl.e, sl.st, f.second);
+          sl = Slot();
+        }
       }
-    }
-    // one chunk of iterations over the slots in a CG solve
-    auto* tab = (BatchSlot<T>*)R->tab_host;
-    unsigned modes = 0;
-    int ncg = 0, last = -1, any = -1;
-    for (int i = 0; i < R->nslots; ++i) {
-      Slot& sl = R->slot[i];
-      BatchSlot<T>& b = tab[i];
-      b = BatchSlot<T>{};
-      b.mode = BATCH_EMPTY;
-      if (sl.ph == PH_CG && sl.mode != BATCH_EMPTY) {
-        const CgBufs<T> bb = slot_bufs<T>(R, i);
-        b = BatchSlot<T>{bb.p, bb.t, bb.g, bb.hd, bb.mask, bb.S, bb.part, bb.sc,
-                         spec_view<T>(sl.e->K).KT, sl.e->K->nx, sl.e->K->ny, sl.it0, sl.mode};
-        modes |= 1u << sl.mode;
-        ++ncg;
-        last = i;
-        any = i;
+      // 2. admission into free slots and the next round
+      {
+        std::unique_lock<std::mutex> lk(S->mu);
+        R->fresh.clear();
+        int active = 0;
+        for (const Slot& sl : R->slot) active += sl.r != nullptr;
+        for (int i = 0; i < R->nslots && !R->ready.empty(); ++i) {
+          if (R->slot[i].r) continue;
+          Req* r = R->ready.front();
+          R->ready.pop_front();
+          Slot& sl = R->slot[i];
+          sl.r = r;
+          sl.e = r->entry;
+          sl.st = r->lent;
+          R->fresh.push_back(i);
+          ++active;
+        }
+        R->active = active;
+        if (active == 0) continue;
       }
-    }
-    hipError_t e = hipSuccess;
-    if (ncg > 0) {
-      const int used = last + 1;
-      e = hipMemcpyAsync(R->tab_dev, tab, used * sizeof(BatchSlot<T>), hipMemcpyHostToDevice,
-                         R->stream);
-      if (e == hipSuccess)
-        e = launch_batch_iterations<T>(R->slot[any].e->K->g, spec_view<T>(R->slot[any].e->K),
-                                       (const BatchSlot<T>*)R->tab_dev, used, modes, kChunk,
-                                       R->stream);
-    }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(R->sc_host, R->sc_dev, R->nslots * sizeof(CgScal), hipMemcpyDeviceToHost,
-                         R->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(R->stream);
-    if (ncg > 0) {
+      fin.clear();
+      const Clock::time_point t0 = Clock::now();
+      hipError_t e = R->prec == BEM_FP64 ? class_launch<double>(R, kChunk, fin)
+                                         : class_launch<float>(R, kChunk, fin);
+      if (e == hipSuccess) e = hipEventRecord(R->done_ev, R->stream);
+      progressed = true;
       std::unique_lock<std::mutex> lk(S->mu);
-      S->chunks += 1;
-      S->slot_chunks += ncg;
-    }
-    for (int i = 0; i < R->nslots && e == hipSuccess; ++i) {
-      bool done_already = false;
-      for (auto& f : finished) done_already |= f.first == i;
-      if (!done_already && R->slot[i].r) e = slot_advance<T>(R, i, kChunk, finished);
-    }
-    if (e != hipSuccess) {   // the stream is unusable: fail every active request
-      hip_fail(e, "batched solve");
-      for (int i = 0; i < R->nslots; ++i)
-        if (R->slot[i].r) finished.push_back({i, BEM_EDEVICE});
-      (void)hipStreamSynchronize(R->stream);
-    }
-    // retire finished slots
-    if (!finished.empty()) {
-      std::unique_lock<std::mutex> lk(S->mu);
-      for (auto& f : finished) {
+      S->eng_launch += secs(t0, Clock::now());
+      if (R->last_chunk_slots > 0) {
+        S->chunks += 1;
+        S->slot_chunks += R->last_chunk_slots;
+      }
+      if (e != hipSuccess) {
+        hip_fail(e, "batched solve");
+        for (int i = 0; i < R->nslots; ++i)
+          if (R->slot[i].r) fin.push_back({i, BEM_EDEVICE});
+      }
+      for (auto& f : fin) {   // setup failures (and launch errors) retire now
         Slot& sl = R->slot[f.first];
         if (!sl.r) continue;
-        if (f.second >= 0) S->batched++;
         complete_locked(S, sl.r, sl.e, sl.st, f.second);
         sl = Slot();
+        R->active--;
       }
-      finished.clear();
+      R->in_flight = e == hipSuccess;
+    }
+    if (!progressed) {
+      // every class has a round on the GPU: wait a little before polling again
+      const Clock::time_point t0 = Clock::now();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->eng_sync += secs(t0, Clock::now());
     }
   }
 }
 
-void runner_main(Runner* R) {
-  if (R->prec == BEM_FP64)
-    runner_loop<double>(R);
-  else
-    runner_loop<float>(R);
-}
+// Largest half-length of the padded transform served on the batched path
+// (grids up to 256 x 256).  Measured on the serving stream with MIXED
+// solves: at 64^2..128^2 one launch per CG kernel for all slots gave 1870
+// against 1420 solves/s for independent solves on four streams, at
+// 129^2..512^2 the two were equal (251 / 252), and above 512^2, where a
+// single solve's kernels already fill the GPU, independent solves were
+// faster (34 against 24 solves/s): their kernels overlap in different phases
+// while a batch moves in lock-step.
+constexpr int kBatchMaxL = 256;
 
 // The class of a request on the batched path, or false for the per-request path.
 bool batch_class(const bem_server_s* S, const bem_request& q, ClassKey* key) {
@@ -587,7 +682,7 @@ bool batch_class(const bem_server_s* S, const bem_request& q, ClassKey* key) {
   while (Mx < 2 * q.nx) Mx <<= 1;
   while (My < 2 * q.ny) My <<= 1;
   Geom g{q.nx, q.ny, Mx / 2, My / 2, 0};
-  if (!batch_geometry(g)) return false;
+  if (!batch_geometry(g) || g.Lx > kBatchMaxL || g.Ly > kBatchMaxL) return false;
   *key = ClassKey{g.Lx, g.Ly, q.prm.precision};
   return true;
 }
@@ -598,10 +693,27 @@ void worker(bem_server_s* S, int slot) {
   for (;;) {
     Req* r = nullptr;
     Entry* e = nullptr;
+    Runner* prep = nullptr;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
         if (S->stop) return;
+        // batched requests first: admit and prepare one for a runner with
+        // room (slots not yet running, ready or being prepared)
+        for (auto& kv : S->runners) {
+          Runner* R = kv.second;
+          if (R->queue.empty() || R->active + (int)R->ready.size() + R->preparing >= R->nslots)
+            continue;
+          e = admit(S, R->queue.front());
+          if (!e) continue;
+          r = R->queue.front();
+          R->queue.pop_front();
+          r->entry = e;
+          R->preparing++;
+          prep = R;
+          break;
+        }
+        if (r) break;
         if (!S->queue.empty()) {
           e = admit(S, S->queue.front());
           if (e) {
@@ -615,6 +727,10 @@ void worker(bem_server_s* S, int slot) {
       r->t_start = Clock::now();
       S->running++;
       S->peak_running = std::max(S->peak_running, S->running);
+    }
+    if (prep) {
+      prepare_batched(S, prep, r, st);
+      continue;
     }
     // build the influence operator if this request created the entry
     int rc = entry_influence(S, r, e);
@@ -692,7 +808,21 @@ int bem_server_create_ex(long long budget_bytes, int n_slots, int batch_slots, b
     }
     S->streams.push_back(s);
   }
+  // the batched path: one launch thread over a few streams (one per hardware
+  // queue of the default HIP configuration)
+  for (int i = 0; batch_slots > 0 && i < 4; ++i) {
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (hipStream_t q : S->streams) hipStreamDestroy(q);
+      for (hipStream_t q : S->engine_streams) hipStreamDestroy(q);
+      delete S;
+      return hip_fail(e, "bem_server_create stream");
+    }
+    S->engine_streams.push_back(s);
+  }
   for (int i = 0; i < n_slots; ++i) S->workers.emplace_back(worker, S, i);
+  if (batch_slots > 0) S->engine = std::thread(engine_loop, S);
   *out = S;
   return BEM_OK;
 }
@@ -750,9 +880,10 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
         lk.lock();
         R = S->runners.find(key)->second;
       } else {
+        nr->stream = S->engine_streams[S->runner_list.size() % S->engine_streams.size()];
         S->runners[key] = nr;
+        S->runner_list.push_back(nr);
         R = nr;
-        nr->th = std::thread(runner_main, nr);
       }
     }
   }
@@ -801,6 +932,9 @@ int bem_server_stats(bem_server_t S, bem_server_stats_t* out) {
   out->queued = (long long)S->queue.size();
   for (auto& kv : S->runners) out->queued += (long long)kv.second->queue.size();
   out->batched = S->batched;
+  out->engine_launch_s = S->eng_launch;
+  out->engine_sync_s = S->eng_sync;
+  out->engine_step_s = S->eng_step;
   out->mean_batch_slots = S->chunks > 0 ? S->slot_chunks / S->chunks : 0.0;
   out->running = S->running;
   out->peak_running = S->peak_running;
@@ -832,6 +966,7 @@ int bem_server_reset_stats(bem_server_t S) {
   S->cache_hits = S->cache_misses = S->evictions = 0;
   S->batched = 0;
   S->chunks = S->slot_chunks = 0;
+  S->eng_launch = S->eng_sync = S->eng_step = 0;
   return BEM_OK;
 }
 
@@ -844,11 +979,12 @@ int bem_server_free(bem_server_t S) {
     S->cv_done.notify_all();
   }
   for (auto& t : S->workers) t.join();
+  if (S->engine.joinable()) S->engine.join();
   for (auto& kv : S->runners) {
-    kv.second->th.join();
     runner_release(kv.second);
     delete kv.second;
   }
+  for (hipStream_t s : S->engine_streams) hipStreamDestroy(s);
   for (auto& kv : S->cache) {
     free_entry(kv.second);
     delete kv.second;

@@ -24,7 +24,7 @@ def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, s
     qps None: all at once (saturation).  Otherwise Poisson arrivals at rate qps.
     batch_slots: solves per batched launch group (0: every request is a solve
     of its own).  Returns a dict of statistics; with want_p also the list of
-    (status, result, pressure) per request under "results"."""
+    (status, result, pressure, contact) per request under "results"."""
     srv = bem.bem_server_create_ex(budget_bytes, n_slots, batch_slots)
     rng = np.random.default_rng(seed)
     ids = []
@@ -42,7 +42,11 @@ def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, s
                               want_p=want_p))
         if progress and (j + 1) % progress == 0:
             print(f"[serving] submitted {j + 1}/{len(requests)}", file=sys.stderr, flush=True)
-    polled = [srv.poll(i) for i in ids]
+    polled = []
+    for j, i in enumerate(ids):
+        polled.append(srv.poll(i))
+        if progress and (j + 1) % progress == 0:
+            print(f"[serving] done {j + 1}/{len(ids)}", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     st = srv.stats().as_dict()
     srv.free()
@@ -50,14 +54,15 @@ def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, s
     st["wall_s"] = t1 - t0
     st["offered_qps"] = qps
     st["status_counts"] = {int(s): statuses.count(s) for s in set(statuses)}
+    st["statuses"] = statuses
     if want_p:
         st["results"] = [(p[0], p[1], p[2], p[3]) for p in polled]
     return st
 
 
 KEYS_SAT = ("solves_per_s", "p50_latency_s", "p99_latency_s", "mean_wait_s", "peak_running",
-            "batched", "mean_batch_slots", "cache_hits", "cache_misses", "evictions",
-            "status_counts", "wall_s")
+            "batched", "mean_batch_slots", "engine_launch_s", "engine_sync_s", "engine_step_s",
+            "cache_hits", "cache_misses", "evictions", "status_counts", "wall_s")
 KEYS_POISSON = ("offered_qps", "solves_per_s", "p50_latency_s", "p99_latency_s", "mean_wait_s",
                 "peak_running", "batched", "mean_batch_slots", "status_counts", "wall_s")
 
@@ -71,6 +76,10 @@ def main():
     ap.add_argument("--batch-slots", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=8.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--phase", choices=("all", "saturation", "poisson"), default="all",
+                    help="saturation runs, Poisson runs (needs --qps), or both")
+    ap.add_argument("--qps", type=float, default=None,
+                    help="Poisson arrival rate (default: 0.8 x the FP64 saturation rate)")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -81,16 +90,20 @@ def main():
            "batch_slots": a.batch_slots, "budget_bytes": budget}
     sat = {}
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        if a.phase == "poisson":
+            break
         s = run_stream(reqs, prec, None, a.slots, budget, batch_slots=a.batch_slots,
-                       progress=1000)
+                       progress=500)
         sat[name] = s["solves_per_s"]
         out[f"{name}_saturation"] = {k: s[k] for k in KEYS_SAT}
         print(f"[serving] {name} saturation {s['solves_per_s']:.1f} solves/s", file=sys.stderr,
               flush=True)
-    qps = 0.8 * sat["fp64"]
+    qps = a.qps if a.qps else 0.8 * sat.get("fp64", 0.0)
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+        if a.phase == "saturation" or qps <= 0:
+            break
         s = run_stream(reqs, prec, qps, a.slots, budget, seed=7, batch_slots=a.batch_slots,
-                       progress=1000)
+                       progress=500)
         out[f"{name}_poisson"] = {k: s[k] for k in KEYS_POISSON}
         print(f"[serving] {name} poisson p99 {s['p99_latency_s']:.3f} s", file=sys.stderr,
               flush=True)
