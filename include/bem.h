@@ -123,7 +123,8 @@ int bem_convolve_dev(bem_influence_t K, int precision, const void* p, void* u, v
  * no allocation of any kind.  The caller still passes p and u (device arrays
  * as for bem_convolve_dev).  The handle's device must be current.
  * Errors: BEM_EINVAL (NULL argument, bad precision, another device current),
- * BEM_EUNSUPPORTED when ny * Lx complex values of the precision (Lx = Mx / 2,
+ * BEM_EUNSUPPORTED when ny (rounded up to even) * Lx complex values of the
+ * precision (Lx = Mx / 2,
  * bem_influence_info) exceed BEM_NOALLOC_SCRATCH_BYTES (16 MiB: up to
  * 1024 x 1024 in FP64, 2048 x 1024 in FP32), BEM_EDEVICE.
  * All calls on one device share the array: calls that overlap on a device

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(128 * NC) void k_col_conv_w(cplx<float>* __restrict
   for (int j = 0; j < Stage::CNT; ++j) y[j] = lds[col_stage_base<P>(Stage::col(j)) + Stage::row(j)];
 #pragma unroll
   for (int j = 0; j < Stage::CNT; ++j)
-    if (Stage::row(j) < ny) S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
+    if (Stage::row(j) < ny) S[Stage::at(j, lx, c0)] = y[j];
 }
 
 }  // namespace bem
@@ -298,9 +298,12 @@ __global__ __launch_bounds__(128 * NC) void k_col_energy_w(const cplx<float>* __
 // workgroup (eight waves, 133 KB of LDS); column cc is staged in regions
 // 4 cc and 4 cc + 1.
 
+// Column cc is staged across regions 4 cc and 4 cc + 1, offset by 16 cc
+// elements: a half-wave of the staging copy holds rows 0..15 of both columns
+// (row pairs, spec_idx order), which then fall on disjoint LDS banks.
 template <int NC>
 __device__ __forceinline__ int quarter_stage_base(int cc) {
-  return 4 * cc * wave_region<32>() + 8 * cc;
+  return 4 * cc * wave_region<32>() + 16 * cc;
 }
 
 // Quarter input for wave (par, half), n = lane + 64 m, from the staged column:
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256 * NC) void k_col_conv_q(cplx<float>* __restrict
                                                          const int* __restrict__ done) {
   constexpr int LY = 4096, P = 32, REG = wave_region<P>();
   constexpr int NT = 256 * NC;
-  static_assert(LY + 8 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
+  static_assert(LY + 16 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
   __shared__ cplx<float> lds[4 * NC * REG];
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(256 * NC) void k_col_conv_q(cplx<float>* __restrict
   }
 #pragma unroll
   for (int j = 0; j < Stage::CNT; ++j)
-    if (Stage::row(j) < ny) S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
+    if (Stage::row(j) < ny) S[Stage::at(j, lx, c0)] = y[j];
 }
 
 // Forward quarter transforms and the spectral energy sum_k KT(k) |T(k)|^2
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(256 * NC) void k_col_energy_q(const cplx<float>* __
                                                            double* __restrict__ part) {
   constexpr int LY = 4096, P = 32, REG = wave_region<P>();
   constexpr int NT = 256 * NC;
-  static_assert(LY + 8 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
+  static_assert(LY + 16 * (NC - 1) <= 2 * REG && 8192 <= 4 * REG, "column regions");
   __shared__ cplx<float> lds[4 * NC * REG];
   __shared__ double red[NT / 64];
   if (done && *done) return;

@@ -76,6 +76,34 @@ __host__ __device__ constexpr int lds_idx(int i) { return LdsLayout<T>::idx(i); 
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 
+// Row spectrum layout: the two rows of a row pair are interleaved per
+// column, spectrum column c of row y at ((y >> 1) lx + c) 2 + (y & 1).  A row
+// sweep (one workgroup per row pair) then writes and reads its pair as one
+// contiguous block, and a column sweep over W adjacent columns moves 2 W
+// complex values per row pair in one piece instead of W per row.  Holds
+// spec_rows(ny) rows (ny rounded up to even).
+__host__ __device__ __forceinline__ size_t spec_idx(int y, int c, int lx) {
+  return ((size_t)(y >> 1) * lx + c) * 2 + (y & 1);
+}
+__host__ __device__ constexpr int spec_rows(int ny) { return ny + (ny & 1); }
+
+// Both rows of a pair at one spectrum column, p = S + spec_idx(2 j, c, lx):
+// one 16-byte access for float (32 bytes for double).  A row sweep stores
+// the pair whole; for an odd ny the padding row's slot is written and never
+// read as data.
+template <typename T>
+struct __align__(4 * sizeof(T)) cpair {
+  cplx<T> a, b;
+};
+template <typename T>
+__device__ __forceinline__ void store_pair(cplx<T>* p, cplx<T> a, cplx<T> b) {
+  *reinterpret_cast<cpair<T>*>(p) = cpair<T>{a, b};
+}
+template <typename T>
+__device__ __forceinline__ cpair<T> load_pair(const cplx<T>* p) {
+  return *reinterpret_cast<const cpair<T>*>(p);
+}
+
 // Block-wide FP64 sum; every thread passes its value, the result is valid in
 // every thread.  Fixed combination order (wave shuffles, then waves in index
 // order), so the result is bitwise reproducible.  `red` holds >= 16 doubles.

@@ -159,14 +159,15 @@ __device__ __forceinline__ void row_r2c_body(Pro& pro, cplx<T>* __restrict__ S, 
   fft_lds<T, L, -1, 2, NTHR, STR>(lds, tw);
   const cplx<T>* E = lds;
   const cplx<T>* O = lds + STR;
-  cplx<T>* Sa = S + (size_t)ya * L;
-  cplx<T>* Sb = S + (size_t)yb * L;
+  // the pair's block of the row spectrum: row a at even, row b at odd slots
+  cplx<T>* Sp = S + spec_idx(ya, 0, L);
   const T half = T(0.5);
   for (int k = threadIdx.x; k < L; k += NTHR) {
+    cplx<T> a, b;
     if (k == 0) {
       const cplx<T> z0 = E[lds_idx<T>(0)], zl = E[lds_idx<T>(L / 2)];
-      Sa[0] = {z0.x, zl.x};
-      if (hasb) Sb[0] = {z0.y, zl.y};
+      a = {z0.x, zl.x};
+      b = {z0.y, zl.y};
     } else {
       const int kp = k >> 1;
       cplx<T> Z, Zp;
@@ -177,9 +178,10 @@ __device__ __forceinline__ void row_r2c_body(Pro& pro, cplx<T>* __restrict__ S, 
         Z = O[lds_idx<T>(kp)];
         Zp = O[lds_idx<T>(L - 1 - kp)];
       }
-      Sa[k] = {half * (Z.x + Zp.x), half * (Z.y - Zp.y)};
-      if (hasb) Sb[k] = {half * (Z.y + Zp.y), half * (Zp.x - Z.x)};
+      a = {half * (Z.x + Zp.x), half * (Z.y - Zp.y)};
+      b = {half * (Z.y + Zp.y), half * (Zp.x - Z.x)};
     }
+    store_pair(Sp + 2 * k, a, b);
   }
   pro.template finish<NTHR>(red, bid);
 }
@@ -200,11 +202,13 @@ __device__ __forceinline__ cplx<T> cload_or0(const cplx<T>* __restrict__ a, size
 }
 
 // Staging of a group of W adjacent spectrum columns c0.. through LDS.
-// Element f = threadIdx.x + j NTHR of the group is (column f % W, row f / W),
-// rows n < LY.  load() issues every load of the thread before any value is
-// used, with rows >= ny read as zero: the same copy written as a loop with
-// the row guard as a branch waits for each load before issuing the next,
-// which leaves one load per thread in flight.
+// Element f = threadIdx.x + j NTHR of the group is (row parity f % 2, column
+// (f / 2) % W, row pair f / 2W): consecutive elements are consecutive in the
+// row spectrum (spec_idx), 2 W values per row pair.  Rows n < LY.  load()
+// issues every load of the thread before any value is used, with rows >= ny
+// read as zero: the same copy written as a loop with the row guard as a
+// branch waits for each load before issuing the next, which leaves one load
+// per thread in flight.
 template <typename T, int LY, int W, int NTHR>
 struct ColStage {
   static constexpr int TOT = W * LY;
@@ -213,13 +217,21 @@ struct ColStage {
   __device__ __forceinline__ static bool valid(int j) {
     return TOT % NTHR == 0 || (int)threadIdx.x + j * NTHR < TOT;
   }
-  __device__ __forceinline__ static int col(int j) { return ((int)threadIdx.x + j * NTHR) % W; }
-  __device__ __forceinline__ static int row(int j) { return ((int)threadIdx.x + j * NTHR) / W; }
+  __device__ __forceinline__ static int col(int j) {
+    return (((int)threadIdx.x + j * NTHR) >> 1) % W;
+  }
+  __device__ __forceinline__ static int row(int j) {
+    const int f = (int)threadIdx.x + j * NTHR;
+    return 2 * ((f >> 1) / W) + (f & 1);
+  }
+  __device__ __forceinline__ static size_t at(int j, int lx, int c0) {
+    return spec_idx(row(j), c0 + col(j), lx);
+  }
   __device__ __forceinline__ void load(const cplx<T>* __restrict__ S, int lx, int ny, int c0) {
 #pragma unroll
     for (int j = 0; j < CNT; ++j) {
       const bool ok = valid(j) && row(j) < ny;
-      x[j] = cload_or0(S, (size_t)row(j) * lx + c0 + col(j), (size_t)c0, ok);
+      x[j] = cload_or0(S, at(j, lx, c0), spec_idx(0, c0, lx), ok);
     }
   }
 };
@@ -318,7 +330,7 @@ __device__ __forceinline__ void col_conv_body(cplx<T>* __restrict__ S, int lx, i
 #pragma unroll
   for (int j = 0; j < Stage::CNT; ++j)
     if (Stage::valid(j) && Stage::row(j) < ny)
-      S[(size_t)Stage::row(j) * lx + c0 + Stage::col(j)] = y[j];
+      S[Stage::at(j, lx, c0)] = y[j];
 }
 
 template <typename T, int LY, int W, int NTHR>
@@ -420,9 +432,9 @@ __device__ __forceinline__ void row_c2r_body(const cplx<T>* __restrict__ S, int 
   if (!epi.template begin<NTHR>(red)) return;
   const int ya = 2 * bid, yb = ya + 1;
   const bool hasb = yb < ny;
-  const cplx<T>* Sa = S + (size_t)ya * L;
-  const cplx<T>* Sb = S + (size_t)yb * L;
-  const cplx<T>* Sbs = hasb ? Sb : Sa;   // a valid row to read when yb is absent
+  // the pair's block of the row spectrum (row b at odd slots; row a stands in
+  // for an absent b)
+  const cplx<T>* Sp = S + spec_idx(ya, 0, L);
   // all loads first (no control flow between them), then the LDS scatter
   constexpr int KPER = (L + NTHR - 1) / NTHR;
   cplx<T> Av[KPER], Bv[KPER];
@@ -430,8 +442,9 @@ __device__ __forceinline__ void row_c2r_body(const cplx<T>* __restrict__ S, int 
   for (int j = 0; j < KPER; ++j) {
     const int k = threadIdx.x + j * NTHR;
     const int ks = k < L ? k : 0;
-    Av[j] = Sa[ks];
-    Bv[j] = Sbs[ks];
+    const cpair<T> ab = load_pair(Sp + 2 * ks);
+    Av[j] = ab.a;
+    Bv[j] = hasb ? ab.b : ab.a;
   }
   // the epilogue's own loads, issued after the spectrum (in-order completion)
   // so that they stay in flight during the transform

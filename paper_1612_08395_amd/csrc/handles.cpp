@@ -61,7 +61,7 @@ int influence_build(bem_influence_s* h) {
 
   // the spectrum is built in the handle's FP64 convolution scratch, which
   // the handle keeps (a free here would wait for the whole device)
-  if ((rc = dev_alloc(h, (void**)&h->S64, (size_t)h->ny * g.Lx * sizeof(cplx<double>),
+  if ((rc = dev_alloc(h, (void**)&h->S64, (size_t)spec_rows(h->ny) * g.Lx * sizeof(cplx<double>),
                       "spectrum scratch")))
     return rc;
   const double scale = h->C / ((double)Mx * (double)My);
@@ -88,7 +88,7 @@ int ensure_io(bem_influence_s* h) {
 }
 
 int convolve_device(bem_influence_s* h, int precision, const void* p, void* u, hipStream_t s) {
-  const size_t ns = (size_t)h->ny * h->g.Lx;
+  const size_t ns = (size_t)spec_rows(h->ny) * h->g.Lx;
   hipError_t e;
   if (precision == BEM_FP64) {
     if (!h->S64) {
@@ -109,7 +109,7 @@ int convolve_device(bem_influence_s* h, int precision, const void* p, void* u, h
 
 int sweep_time(bem_influence_s* h, int precision, int which, int reps, hipStream_t s, double* ms) {
   const size_t n = (size_t)h->nx * h->ny;
-  const size_t ns = (size_t)h->ny * h->g.Lx;
+  const size_t ns = (size_t)spec_rows(h->ny) * h->g.Lx;
   int rc;
   hipError_t e;
   if (precision == BEM_FP64) {

@@ -62,7 +62,7 @@ extern "C" int bem_convolve_dev_noalloc(bem_influence_t K, int precision, const 
   if (dev < 0 || dev >= kMaxDevices)
     return set_error(BEM_EUNSUPPORTED, "bem_convolve_dev_noalloc: device index %d", dev);
   const size_t cs = precision == BEM_FP64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
-  const size_t need = (size_t)K->ny * K->g.Lx * cs;
+  const size_t need = (size_t)spec_rows(K->ny) * K->g.Lx * cs;
   if (need > (size_t)BEM_NOALLOC_SCRATCH_BYTES)
     return set_error(BEM_EUNSUPPORTED,
                      "bem_convolve_dev_noalloc: the %d x %d grid needs %zu scratch bytes in this "

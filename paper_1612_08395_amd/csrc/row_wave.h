@@ -83,8 +83,7 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_r2c_w(Pro pro_arg,
     }
   }
   if (threadIdx.x == 0) Zp[0] = E[L / 2];   // k = 0: Z[Lx] for the packed slot
-  cplx<float>* Sa = S + (size_t)ya * L;
-  cplx<float>* Sb = S + (size_t)yb * L;
+  cplx<float>* Sp = S + spec_idx(ya, 0, L);   // the pair's block, rows interleaved
   const float half = 0.5f;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -97,8 +96,7 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_r2c_w(Pro pro_arg,
       a = {half * (Z[j].x + Zp[j].x), half * (Z[j].y - Zp[j].y)};
       b = {half * (Z[j].y + Zp[j].y), half * (Zp[j].x - Z[j].x)};
     }
-    Sa[k] = a;
-    if (hasb) Sb[k] = b;
+    store_pair(Sp + 2 * k, a, b);
   }
   pro.template finish<NTHR>(red, blockIdx.x);
 }
@@ -120,14 +118,13 @@ __global__ __launch_bounds__(kRowWaveThreads, 2) void k_row_c2r_w(const cplx<flo
   if (!epi.template begin<NTHR>(red)) return;
   const int ya = 2 * blockIdx.x, yb = ya + 1;
   const bool hasb = yb < ny;
-  const cplx<float>* Sa = S + (size_t)ya * L;
-  const cplx<float>* Sbs = hasb ? S + (size_t)yb * L : Sa;
+  const cplx<float>* Sp = S + spec_idx(ya, 0, L);   // the pair's block, rows interleaved
   cplx<float> Av[PER], Bv[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int k = threadIdx.x + j * NTHR;
-    Av[j] = Sa[k];
-    Bv[j] = Sbs[k];
+    const cpair<float> ab = load_pair(Sp + 2 * (threadIdx.x + j * NTHR));
+    Av[j] = ab.a;
+    Bv[j] = hasb ? ab.b : ab.a;
   }
   // the epilogue's loads stay in flight during the transform
   epi.template prefetch<NTHR>(ya, yb, hasb, nx);

@@ -774,11 +774,11 @@ int bem_footprint(int nx, int ny, int precision, long long* influence_bytes,
   // scratch the handle keeps from its build
   if (influence_bytes)
     *influence_bytes = n * 8 + (Lx + 1) * kpitch * 12 + (long long)(Mx + My + Ly + Lx) * 24 +
-                       (long long)ny * Lx * 16;
+                       (long long)(ny + (ny & 1)) * Lx * 16;
   const long long ts = precision == BEM_FP64 ? 8 : 4;
   if (state_bytes)
     *state_bytes = n * (1 + 8 + 8) + state_partial_bytes() + 512 + 4 * n * ts +
-                   (long long)ny * Lx * 2 * ts;
+                   (long long)(ny + (ny & 1)) * Lx * 2 * ts;
   return BEM_OK;
 }
 

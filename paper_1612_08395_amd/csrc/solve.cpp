@@ -77,7 +77,8 @@ int bem::ensure_precision(bem_state_s* st, int precision, hipStream_t s) {
   if ((rc = salloc(st, &st->t, st->n * ts, "direction"))) return rc;
   if ((rc = salloc(st, &st->g, st->n * ts, "gap"))) return rc;
   if ((rc = salloc(st, &st->hd, st->n * ts, "gap profile"))) return rc;
-  if ((rc = salloc(st, &st->S, (size_t)st->K->ny * st->K->g.Lx * cs, "row spectrum"))) return rc;
+  if ((rc = salloc(st, &st->S, (size_t)spec_rows(st->K->ny) * st->K->g.Lx * cs, "row spectrum")))
+    return rc;
   st->precision = precision;
   return BEM_OK;
 }
