@@ -140,12 +140,16 @@ def roofline(bem, K, clock, torch):
     write the ny x Lx complex row spectrum and read the (Lx+1) x (Ly+1) real
     kernel spectrum.  Duration: the solver clock's mean over every column
     launch that did work in one sweep of the timed workload (HIP events on
-    the solver stream)."""
+    the solver stream), less the cost of one event record on the stream: in
+    displacement control the last two events of an iteration are recorded
+    back to back, and their interval is that cost."""
     info = K.info
     Lx, Ly = info.Mx // 2, info.My // 2
     bytes_per_launch = 2 * info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
     n_col = clock.launches[1]
-    ms = clock.ms[1] / n_col
+    ev_ms = clock.ms[5] / max(1, clock.launches[5])
+    ms_raw = clock.ms[1] / n_col
+    ms = ms_raw - ev_ms
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -156,32 +160,55 @@ def roofline(bem, K, clock, torch):
             traffic = tr.get("bytes_per_launch")
     stream = torch.cuda.current_stream()
     iso = bem.bem_kernel_time(K, bem.BEM_MIXED, 1, reps=50, stream=stream)
+    # practical ceilings beside the published peak: plain device copies
+    # (torch), read + written bytes over their time, one moving as many bytes
+    # as a column launch (its buffers stay in the last-level cache between
+    # copies, as the CG loop's ~0.12 GB working set at 2048^2 can) and one of
+    # 2 x 1 GiB (HBM)
+    def copy_gbps(nbytes, reps):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        t_a, t_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_a.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        t_b.record()
+        torch.cuda.synchronize()
+        return 2 * src.numel() * 4 * reps / (t_a.elapsed_time(t_b) * 1e-3) / 1e9
+
+    copy_same = copy_gbps(bytes_per_launch // 2, 50)
+    copy_hbm = copy_gbps(1 << 30, 5)
     # the same launches against the usable fp32 vector peak: 4 FFTs of Ly
     # points per column (5 n log2 n flops each) and the spectrum multiply;
     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, non-packed fp32
     flop = Lx * (4 * 5 * Ly * math.log2(Ly) + 4 * Ly)
     tflops = flop / (ms * 1e-3) / 1e12
-    loop = {name: round(clock.ms[k] / max(1, clock.launches[k]) * 1e3, 2)
+    loop = {name: round((clock.ms[k] / max(1, clock.launches[k]) - ev_ms) * 1e3, 2)
             for k, name in enumerate(("update_r2c", "column_conv", "gap_c2r", "direction_r2c",
-                                      "column_energy", "none_event_gap"))}
+                                      "column_energy"))}
     # second convolution's column kernel: reads S and the spectrum quarter
     e_bytes = info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
-    e_ms = clock.ms[4] / max(1, clock.launches[4])
+    e_ms = clock.ms[4] / max(1, clock.launches[4]) - ev_ms
     return {"bound": "hbm", "kernel": "k_col_conv_w<2048,4> (column sweep, FP32)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "ms_per_launch": round(ms, 5), "launches_timed": n_col,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "timing": "HIP events on the solver stream around each column launch of one "
-                      "sweep of the timed workload (run after the timed steps: the events "
-                      "cost ~10% of a sweep), launches past convergence excluded",
+                      "sweep of the timed workload (run after the timed steps), launches past "
+                      "convergence excluded, less the interval of two events recorded back to "
+                      "back (the event's own cost on the stream)",
+            "ms_per_launch_events": round(ms_raw, 5), "event_record_ms": round(ev_ms, 5),
             "isolated_ms_per_launch": round(iso, 5),
+            "device_copy_GBps": {"same_bytes": round(copy_same, 1), "2x1GiB": round(copy_hbm, 1)},
+            "frac_of_device_copy": round(achieved / copy_same, 4),
             "alu_view": {"flop_per_launch": round(flop), "achieved": round(tflops, 2),
                          "peak": 78.6, "unit": "TFLOP/s", "frac": round(tflops / 78.6, 4)},
             "loop_us_per_launch": loop,
             "column_energy": {"ms_per_launch": round(e_ms, 5), "algorithmic_bytes_per_launch":
                               e_bytes, "GBps": round(e_bytes / (e_ms * 1e-3) / 1e9, 1)},
-            "loop_us_per_iteration": round(clock.loop_ms() / clock.iterations * 1e3, 2),
+            "loop_us_per_iteration_events": round(clock.loop_ms() / clock.iterations * 1e3, 2),
             "gap_shift_launches": clock.shifts,
             "gap_shift_us_per_launch": round(clock.shift_ms / max(1, clock.shifts) * 1e3, 2),
             "skipped_launches": clock.skipped,
@@ -321,12 +348,15 @@ def big_grid(bem, torch, depths_n=5):
     del p32, p64
     K.free()
     iters = sum(r["iters"] for r in res)
-    col_ms = clk.ms[1] / clk.launches[1]
+    # event intervals less the cost of one event record (the interval of the
+    # two events recorded back to back at the end of each iteration)
+    ev_ms = clk.ms[5] / max(1, clk.launches[5])
+    col_ms = clk.ms[1] / clk.launches[1] - ev_ms
     col_bytes = 2 * n * n * 8 + (n + 1) * (n + 1) * 4
     return {"n": n, "padded": 2 * n, "k": -0.3, "nu": 0.25, "seed": 8395,
             "depths": depths_n, "d_max": dq, "solves_per_s": round(depths_n / t, 3),
             "iters_per_solve": round(iters / depths_n, 2),
-            "loop_us_per_iteration": round(clk.loop_ms() / clk.iterations * 1e3, 2),
+            "loop_us_per_iteration": round(t / iters * 1e6, 2),
             "loop_GBps_algorithmic": round(sum(loop_bytes(r["n_contact"] / (n * n)) * n * n
                                                * r["iters"] for r in res) / t / 1e9, 1),
             "column_us_per_launch": round(col_ms * 1e3, 2),
@@ -480,7 +510,8 @@ def serving(count, slots, bem):
 
 
 def profile_kernels(bem, torch):
-    """Few launches of each sweep kernel at 2048^2 (for rocprofv3 --pmc), one
+    """Few launches of each sweep kernel at 2048^2 and of the FP32 sweeps at
+    4096^2 (for rocprofv3 --pmc), one
     mixed-precision solve of the bench workload at the deepest depth (the
     fused CG kernels), and a plain device copy of 2^28 floats (1 GiB read +
     1 GiB written) whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
@@ -489,6 +520,11 @@ def profile_kernels(bem, torch):
     for prec, name in ((bem.BEM_MIXED, "f32"), (bem.BEM_FP64, "f64")):
         for which, kname in ((0, "row_r2c"), (1, "col_conv"), (2, "row_c2r")):
             out[f"{kname}_{name}_ms"] = bem.bem_kernel_time(K, prec, which, reps=4)
+    # the FP32 sweeps of the 4096^2 workload (k = -0.3, nu = 0.25)
+    K4 = bem.bem_influence(4096, 4096, L / 4096, -0.3, 0.25)
+    for which, kname in ((0, "row_r2c"), (1, "col_conv"), (2, "row_c2r"), (3, "col_energy")):
+        out[f"{kname}_f32_4096_ms"] = bem.bem_kernel_time(K4, bem.BEM_MIXED, which, reps=2)
+    K4.free()
     h_dev = torch.tensor(workload(), dtype=torch.float64, device="cuda")
     _, res = bem.bem_solve_dev(K, h_dev, bem.bem_params_init(d=D10, precision=bem.BEM_MIXED))
     out["solve_iters"] = res.iters
@@ -606,7 +642,10 @@ def main():
                             f"(chain c solves depths c, c + {args.chains}, ...)"},
         "single_chain": {"value": round(N_DEPTHS * args.steps / t32s, 3), "unit": "solves/s",
                          "iters_per_solve": round(sum(x["iters"] for x in res32s[-1])
-                                                  / N_DEPTHS, 2)},
+                                                  / N_DEPTHS, 2),
+                         # whole sweep time (no events) per CG iteration
+                         "loop_us_per_iteration": round(
+                             t32s / args.steps / sum(x["iters"] for x in res32s[-1]) * 1e6, 2)},
         "roofline": roof,
         "fp64": {"value": round(solves64, 3), "unit": "solves/s", "steps": args.fp64_steps,
                  "chains": 1,

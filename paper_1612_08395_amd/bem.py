@@ -342,7 +342,8 @@ _f_kernel_time = _sig("bem_kernel_time", _c_int, [_vp, _c_int, _c_int, _c_int, _
 
 
 def bem_kernel_time(K, precision, which, reps=20, stream=None):
-    """Average ms of one convolution sweep kernel (0 R2C, 1 column, 2 C2R)."""
+    """Average ms of one convolution sweep kernel (0 R2C, 1 column, 2 C2R,
+    3 column spectral energy)."""
     ms = _c_double()
     _check(_f_kernel_time(K.handle, int(precision), int(which), int(reps), _stream(stream),
                           ctypes.byref(ms)))
