@@ -190,7 +190,7 @@ def roofline(bem, K, clock, torch):
     # second convolution's column kernel: reads S and the spectrum quarter
     e_bytes = info.ny * Lx * 8 + (Lx + 1) * (Ly + 1) * 4
     e_ms = clock.ms[4] / max(1, clock.launches[4]) - ev_ms
-    return {"bound": "hbm", "kernel": "k_col_conv_w<2048,4> (column sweep, FP32)",
+    return {"bound": "hbm", "kernel": "k_col_conv_w<2048,2> (column sweep, FP32)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "ms_per_launch": round(ms, 5), "launches_timed": n_col,

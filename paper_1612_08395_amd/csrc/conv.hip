@@ -37,11 +37,16 @@ int row_wave_enabled() {
   return on;
 }
 
-// Tuning knob: BEM_COL_NC = 2 or 4 columns per workgroup of the wave kernel.
+// Tuning knob: BEM_COL_NC = 2 (default) or 4 columns per workgroup of the
+// wave column kernel at Ly = 2048.  Two columns (4 waves, 68 KB of LDS) let
+// two workgroups share a CU, which are not in step; with the row spectrum's
+// interleaved row pairs each still moves 32-byte pieces.  Measured at 2048^2:
+// 36.4 against 37.9 us per launch.  The spectral-energy kernel keeps four
+// columns (no gain measured with two: 22.2 against 21.8 us).
 int col_wave_nc() {
   static const int nc = [] {
     const char* v = getenv("BEM_COL_NC");
-    return (v && atoi(v) == 2) ? 2 : 4;
+    return (v && atoi(v) == 4) ? 4 : 2;
   }();
   return nc;
 }
@@ -132,12 +137,12 @@ hipError_t launch_col_energy(const Geom& g, const SpecView<T>& K, const cplx<T>*
                              const int* done, double* part, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     const int w = energy_wave_width<T>(g);
-    if (w == 4) {
+    if (g.Ly == 2048 && w == 4) {
       hipLaunchKernelGGL((k_col_energy_w<2048, 4>), dim3(g.Lx / 4), dim3(512), 0, s, S, g.Lx, g.ny,
                          K.KT, g.kpitch, K.twy, K.twly, done, part);
       return hipGetLastError();
     }
-    if (w == 2) {
+    if (g.Ly == 4096 && w == 2) {
       hipLaunchKernelGGL((k_col_energy_q<2>), dim3(g.Lx / 2), dim3(512), 0, s, S, g.Lx, g.ny, K.KT,
                          g.kpitch, K.twy, K.twly, done, part);
       return hipGetLastError();

@@ -27,7 +27,7 @@ CSRC = os.path.join(HERE, "csrc")
 # sources whose change invalidates stored counter readings of the sweep kernels
 SWEEP_SOURCES = ("conv_kernels.h", "fft_lds.h", "wave_fft.h", "col_wave.h", "row_wave.h", "common.h",
                  "launch.h", "conv.hip")
-COLUMN_KERNEL = "k_col_conv_w<2048, 4>"
+COLUMN_KERNEL = "k_col_conv_w<2048, 2>"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
