@@ -466,7 +466,8 @@ def serving(count, slots, bem):
     saturation run once more without batching (every request a solve of its
     own) for comparison; and the requests the MIXED path stopped at its
     rounding floor (BEM_EFLOOR), solved alone in both precisions, with their
-    pressure difference."""
+    pressure difference; then loading curves of 40 of the requests with and
+    without server sessions (serving.run_curves)."""
     from paper_1612_08395_amd import inputs
     from paper_1612_08395_amd.serving import KEYS_POISSON, KEYS_SAT, run_stream
     reqs = inputs.serving_requests(count, 2024)
@@ -506,6 +507,14 @@ def serving(count, slots, bem):
                        if nrm > 0 else 0.0,
                        "contact_mixed": c32, "contact_fp64": c64})
     out["mixed_floor_requests"] = floors
+    # loading curves (8 steps each; adhesive requests 4 loading + 4 pull-off
+    # steps) of the first 40 requests, MIXED: one server session per curve
+    # (state resident on the device, each step warm-started) against every
+    # step an independent cold request
+    from paper_1612_08395_amd.serving import run_curves
+    cur = reqs[:40]
+    out["curves_mixed"] = {"sessions": run_curves(cur, bem.BEM_MIXED, True, n_slots=slots),
+                           "independent": run_curves(cur, bem.BEM_MIXED, False, n_slots=slots)}
     return out
 
 

@@ -329,8 +329,9 @@ typedef struct {
  *  - Per-request path: every other request (larger grids, load control, or
  *    all requests when batch_slots = 0) is a bem_solve of its own on one of
  *    n_slots (1..16) worker threads, each with its own non-blocking stream.
- * Every request is solved from a cold start with the kernels and order of
- * bem_solve, so its result does not depend on what else runs.
+ * Every request outside a session (below) is solved from a cold start with
+ * the kernels and order of bem_solve, so its result does not depend on what
+ * else runs.
  * batch_slots: 0..64.
  */
 int bem_server_create_ex(long long budget_bytes, int n_slots, int batch_slots, bem_server_t* out);
@@ -339,6 +340,34 @@ int bem_server_create(long long budget_bytes, int n_slots, bem_server_t* out);
 /* Queue a request; *id identifies it.  BEM_ENOMEM if it can never fit the
  * budget, BEM_EINVAL for a bad grid. */
 int bem_server_submit(bem_server_t srv, const bem_request* req, long long* id);
+/*
+ * Sessions: the solver state resident on the device across requests.  A
+ * client that solves one indenter through a sequence of loads (a loading /
+ * unloading curve, Section 3.1) opens a session and submits its requests to
+ * it.  The server keeps one solver state for the session between its
+ * requests and runs them one at a time, in submission order, on the
+ * per-request path: each starts from the previous request's pressure and
+ * contact set (the warm start of bem_solve with a state), and, when its gap
+ * profile is the same as the previous request's, from that request's gap
+ * shifted to the new indentation, exactly as the steps of bem_sweep (a
+ * sequence of requests then gives bem_sweep's results bitwise).  Loading
+ * steps are non-adhesive requests; pull-off steps are adhesive requests,
+ * which hold the state's contact set fixed (bem_solve).
+ *
+ * bem_server_session_open: *session identifies the new session (> 0).
+ * bem_server_submit_session: as bem_server_submit; the first request fixes
+ *   the session's grid, material and precision, later ones must match
+ *   (BEM_EINVAL otherwise, or for an unknown or closed session).  Requests
+ *   of other clients keep running while one of the session's waits for its
+ *   predecessor.  Poll them with bem_server_poll.
+ * bem_server_session_close: no more requests; the state returns to the
+ *   server's pool once the session's last request has completed.  An open
+ *   session keeps its influence operator and state reserved in the budget.
+ */
+int bem_server_session_open(bem_server_t srv, long long* session);
+int bem_server_submit_session(bem_server_t srv, long long session, const bem_request* req,
+                              long long* id);
+int bem_server_session_close(bem_server_t srv, long long session);
 /* Returns 1 while the request is pending (wait = 0), else 0 with *res and
  * *status (the bem_solve status) filled in; the id is then released.  With
  * wait != 0 blocks until the request is done. */

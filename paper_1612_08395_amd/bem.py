@@ -416,6 +416,10 @@ _f_server_create = _sig("bem_server_create", _c_int, [ctypes.c_longlong, _c_int,
 _f_server_create_ex = _sig("bem_server_create_ex", _c_int, [ctypes.c_longlong, _c_int, _c_int,
                                                             ctypes.POINTER(_vp)])
 _f_server_submit = _sig("bem_server_submit", _c_int, [_vp, ctypes.POINTER(Request), _llp])
+_f_server_session_open = _sig("bem_server_session_open", _c_int, [_vp, _llp])
+_f_server_submit_session = _sig("bem_server_submit_session", _c_int,
+                                [_vp, ctypes.c_longlong, ctypes.POINTER(Request), _llp])
+_f_server_session_close = _sig("bem_server_session_close", _c_int, [_vp, ctypes.c_longlong])
 _f_server_poll = _sig("bem_server_poll", _c_int, [_vp, ctypes.c_longlong, _c_int,
                                                   ctypes.POINTER(Result), ctypes.POINTER(_c_int)])
 _f_server_stats = _sig("bem_server_stats", _c_int, [_vp, ctypes.POINTER(ServerStats)])
@@ -451,7 +455,10 @@ class Server:
     def handle(self):
         return self._h
 
-    def submit(self, nx, ny, dx, k, nu, h, prm, dy=None, E0=1.0, c0=1.0, want_p=False):
+    def submit(self, nx, ny, dx, k, nu, h, prm, dy=None, E0=1.0, c0=1.0, want_p=False,
+               session=None):
+        """Queue a request (bem_server_submit), or with `session` a request of
+        that session (bem_server_submit_session); returns its id."""
         h = _host(h, (ny, nx))
         p = np.empty((ny, nx)) if want_p else None
         c = np.empty((ny, nx), dtype=np.uint8) if want_p else None
@@ -460,9 +467,22 @@ class Server:
                       p.ctypes.data_as(_dp) if p is not None else None,
                       c.ctypes.data_as(_u8p) if c is not None else None)
         rid = ctypes.c_longlong()
-        _check(_f_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        if session is None:
+            _check(_f_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        else:
+            _check(_f_server_submit_session(self._h, int(session), ctypes.byref(req),
+                                            ctypes.byref(rid)))
         self._keep[rid.value] = (p, c)
         return rid.value
+
+    def session_open(self):
+        """bem_server_session_open: a session id."""
+        sid = ctypes.c_longlong()
+        _check(_f_server_session_open(self._h, ctypes.byref(sid)))
+        return sid.value
+
+    def session_close(self, session):
+        _check(_f_server_session_close(self._h, int(session)))
 
     def poll(self, rid, wait=True):
         """None while pending (wait=False), else (status, Result, p, contact)."""

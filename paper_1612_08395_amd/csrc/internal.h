@@ -73,6 +73,11 @@ int set_error(int code, const char* fmt, ...);
 void clear_error();
 int hip_fail(hipError_t e, const char* what);
 
+// A solve on the gap profile the state already holds from its previous
+// solve, as the next step of a sweep (solve.cpp; serving sessions).
+int solve_same_h(bem_influence_t K, const bem_params* prm, bem_state_t st, double* p_out,
+                 unsigned char* c_out, bem_result* res, hipStream_t s);
+
 // Bytes of a solver state's partial-sum buffer (solve.cpp; footprint model).
 long long state_partial_bytes();
 

@@ -19,6 +19,13 @@
 //
 // Each request is solved from a cold start with the same kernels in the same
 // order as bem_solve, so its result does not depend on what else runs.
+//
+// Sessions: a client that solves one indenter through a sequence of loads
+// opens a session; the server keeps one solver state on the device for it
+// between its requests (per-request path, one at a time, in submission
+// order), so each request starts from the previous one's pressure and
+// contact set, and from its gap when the profile is the same (a step of a
+// sweep, as in bem_sweep).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,6 +71,8 @@ struct Entry {
   unsigned long long last_use = 0;
 };
 
+struct Session;
+
 struct Req {
   long long id;
   bem_request r;
@@ -76,6 +85,25 @@ struct Req {
   bem_state_t lent = nullptr;  // pooled state handed over at admission
   bool builder = false;        // this request created the cache entry
   Entry* entry = nullptr;      // batched path: admitted entry (prepared by a worker)
+  Session* session = nullptr;  // the session this request belongs to, if any
+};
+
+// A session's resident solver state.  The first request fixes the grid,
+// material and precision and is admitted like any request; the session then
+// holds that entry (one in_use count) and the state until it is closed and
+// its last request has completed.  busy and pending change under the server
+// lock; h_prev only in the worker running the session's request.
+struct Session {
+  long long id = 0;
+  bool keyed = false;
+  Key key;
+  int prec = 0;
+  Entry* e = nullptr;
+  bem_state_t st = nullptr;
+  std::vector<double> h_prev;  // gap profile of the state's last solve
+  int pending = 0;             // submitted and not yet completed
+  bool busy = false;           // one of its requests is running
+  bool closed = false;
 };
 
 }  // namespace
@@ -101,6 +129,8 @@ struct bem_server_s {
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> queue;
   std::unordered_map<long long, Req*> reqs;
+  std::unordered_map<long long, Session*> sessions;
+  long long next_session = 1;
   std::map<Key, Entry*> cache;
   long long used = 0;
   long long next_id = 1;
@@ -182,8 +212,17 @@ Entry* admit(bem_server_s* S, Req* r) {
 
 // Bookkeeping of a finished request (lock held): the state returns to its
 // entry's pool, statistics, wake the poller and the admission loops.
+void release_session_locked(bem_server_s* S, Session* ss);
+
 void complete_locked(bem_server_s* S, Req* r, Entry* e, bem_state_t state, int rc) {
-  if (e) {
+  if (Session* ss = r->session) {
+    // the session keeps the state and its hold on the entry
+    ss->st = state;
+    ss->busy = false;
+    ss->pending--;
+    if (e) e->last_use = ++S->tick;
+    if (ss->closed && ss->pending == 0) release_session_locked(S, ss);
+  } else if (e) {
     if (state) e->free_states[r->r.prm.precision].push_back(state);
     e->in_use--;
     e->last_use = ++S->tick;
@@ -210,6 +249,24 @@ void complete_locked(bem_server_s* S, Req* r, Entry* e, bem_state_t state, int r
   r->h.shrink_to_fit();
   S->cv_done.notify_all();
   S->cv_work.notify_all();
+}
+
+// A closed session without pending requests (lock held): its state goes to
+// the entry's pool, its hold on the entry ends.
+void release_session_locked(bem_server_s* S, Session* ss) {
+  if (Entry* e = ss->e) {
+    if (ss->st) e->free_states[ss->prec].push_back(ss->st);
+    e->in_use--;
+    e->last_use = ++S->tick;
+    if (!e->K && !e->building && e->in_use == 0) {  // failed build: drop the entry
+      S->cache.erase(e->key);
+      S->used -= e->bytes;
+      free_entry(e);
+      delete e;
+    }
+  }
+  S->sessions.erase(ss->id);
+  delete ss;
 }
 
 // Influence operator of an admitted request's entry: built here when the
@@ -714,14 +771,28 @@ void worker(bem_server_s* S, int slot) {
           break;
         }
         if (r) break;
-        if (!S->queue.empty()) {
-          e = admit(S, S->queue.front());
-          if (e) {
-            r = S->queue.front();
-            S->queue.pop_front();
-            break;
+        // per-request path, in submission order; a request whose session is
+        // busy waits for its predecessor without holding up the others
+        for (auto qi = S->queue.begin(); qi != S->queue.end(); ++qi) {
+          Req* c = *qi;
+          Session* ss = c->session;
+          if (ss && ss->busy) continue;
+          Entry* ce = (ss && ss->e) ? ss->e : admit(S, c);
+          if (!ce) break;   // memory: admission keeps the queue's order
+          if (ss) {
+            ss->busy = true;
+            if (!ss->e) {   // the session's first request: its admission is the session's
+              ss->e = ce;
+              ss->st = c->lent;
+              c->lent = nullptr;
+            }
           }
+          e = ce;
+          r = c;
+          S->queue.erase(qi);
+          break;
         }
+        if (r) break;
         S->cv_work.wait(lk);
       }
       r->t_start = Clock::now();
@@ -734,9 +805,24 @@ void worker(bem_server_s* S, int slot) {
     }
     // build the influence operator if this request created the entry
     int rc = entry_influence(S, r, e);
-    bem_state_t state = r->lent;
+    Session* ss = r->session;
+    bem_state_t state = ss ? ss->st : r->lent;
     if (rc == BEM_OK && !state) rc = bem_state_create(e->K, &state);
-    if (rc == BEM_OK) {
+    if (rc == BEM_OK && ss) {
+      // warm start from the session's previous solve; from its gap as well
+      // when the profile is the same
+      if (!ss->h_prev.empty() && ss->h_prev == r->h)
+        rc = solve_same_h(e->K, &r->r.prm, state, r->r.p_out, r->r.contact_out, &r->res, st);
+      else
+        rc = bem_solve(e->K, r->h.data(), &r->r.prm, state, r->r.p_out, r->r.contact_out,
+                       nullptr, &r->res, st);
+      if (rc < 0) {
+        bem_state_reset(state);   // the next request starts cold
+        ss->h_prev.clear();
+      } else {
+        ss->h_prev.swap(r->h);
+      }
+    } else if (rc == BEM_OK) {
       // every request is a fresh (cold-start) solve, as if solved alone
       bem_state_reset(state);
       rc = bem_solve(e->K, r->h.data(), &r->r.prm, state, r->r.p_out, r->r.contact_out, nullptr,
@@ -827,7 +913,7 @@ int bem_server_create_ex(long long budget_bytes, int n_slots, int batch_slots, b
   return BEM_OK;
 }
 
-int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
+static int submit_impl(bem_server_t S, long long session, const bem_request* req, long long* id) {
   clear_error();
   if (!S || !req || !id || !req->h) return set_error(BEM_EINVAL, "bem_server_submit: NULL argument");
   const bem_request& q = *req;
@@ -848,10 +934,11 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
     return set_error(BEM_ENOMEM, "bem_server_submit: request needs %lld bytes, budget %lld",
                      fi + fs, S->budget);
   }
-  // the batched path: the runner of the request's class (made on first use)
+  // the batched path: the runner of the request's class (made on first use);
+  // a session's requests stay on the per-request path
   ClassKey key;
   Runner* R = nullptr;
-  if (batch_class(S, q, &key)) {
+  if (session == 0 && batch_class(S, q, &key)) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       auto it = S->runners.find(key);
@@ -888,6 +975,27 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
     }
   }
   std::unique_lock<std::mutex> lk(S->mu);
+  if (session != 0) {
+    auto si = S->sessions.find(session);
+    if (si == S->sessions.end() || si->second->closed) {
+      delete r;
+      return set_error(BEM_EINVAL, "bem_server_submit_session: unknown or closed session %lld",
+                       session);
+    }
+    Session* ss = si->second;
+    const Key k{q.nx, q.ny, q.dx, q.dy, q.k, q.nu, q.E0, q.c0};
+    if (ss->keyed && (k != ss->key || q.prm.precision != ss->prec)) {
+      delete r;
+      return set_error(BEM_EINVAL,
+                       "bem_server_submit_session: grid, material and precision must be those "
+                       "of the session's first request");
+    }
+    ss->keyed = true;
+    ss->key = k;
+    ss->prec = q.prm.precision;
+    ss->pending++;
+    r->session = ss;
+  }
   r->id = S->next_id++;
   r->t_submit = Clock::now();
   if (!S->have_first) {
@@ -900,6 +1008,45 @@ int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
   else
     S->queue.push_back(r);
   *id = r->id;
+  S->cv_work.notify_all();
+  return BEM_OK;
+}
+
+int bem_server_submit(bem_server_t S, const bem_request* req, long long* id) {
+  return submit_impl(S, 0, req, id);
+}
+
+int bem_server_session_open(bem_server_t S, long long* session) {
+  clear_error();
+  if (!S || !session) return set_error(BEM_EINVAL, "bem_server_session_open: NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto* ss = new Session();
+  ss->id = S->next_session++;
+  S->sessions[ss->id] = ss;
+  *session = ss->id;
+  return BEM_OK;
+}
+
+int bem_server_submit_session(bem_server_t S, long long session, const bem_request* req,
+                              long long* id) {
+  if (session <= 0) {
+    clear_error();
+    return set_error(BEM_EINVAL, "bem_server_submit_session: invalid session %lld", session);
+  }
+  return submit_impl(S, session, req, id);
+}
+
+int bem_server_session_close(bem_server_t S, long long session) {
+  clear_error();
+  if (!S) return set_error(BEM_EINVAL, "bem_server_session_close: NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto si = S->sessions.find(session);
+  if (si == S->sessions.end() || si->second->closed)
+    return set_error(BEM_EINVAL, "bem_server_session_close: unknown or closed session %lld",
+                     session);
+  Session* ss = si->second;
+  ss->closed = true;
+  if (ss->pending == 0) release_session_locked(S, ss);
   S->cv_work.notify_all();
   return BEM_OK;
 }
@@ -985,6 +1132,18 @@ int bem_server_free(bem_server_t S) {
     delete kv.second;
   }
   for (hipStream_t s : S->engine_streams) hipStreamDestroy(s);
+  // session states go back to their entries' pools (freed with them)
+  for (auto& kv : S->sessions) {
+    Session* ss = kv.second;
+    if (ss->st) {
+      if (ss->e)
+        ss->e->free_states[ss->prec].push_back(ss->st);
+      else
+        bem_state_free(ss->st);
+    }
+    delete ss;
+  }
+  S->sessions.clear();
   for (auto& kv : S->cache) {
     free_entry(kv.second);
     delete kv.second;

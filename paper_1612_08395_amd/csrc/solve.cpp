@@ -515,6 +515,15 @@ int upload_h(bem_state_t st, const double* h, hipStream_t s) {
 
 }  // namespace
 
+// A solve on the gap profile the state already holds (the previous solve's),
+// as the next step of a sweep (see sweep_steps); host outputs.
+int bem::solve_same_h(bem_influence_t K, const bem_params* prm, bem_state_t st, double* p_out,
+                      unsigned char* c_out, bem_result* res, hipStream_t s) {
+  clear_error();
+  if (!K || !prm || !st) return set_error(BEM_EINVAL, "solve_same_h: NULL argument");
+  return solve_common(K, st->h64, prm, st, p_out, c_out, nullptr, true, res, s, true);
+}
+
 extern "C" {
 
 void bem_params_init(bem_params* prm) {

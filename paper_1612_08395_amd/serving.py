@@ -1,5 +1,6 @@
 """Driver of the serving loop (bem_server_*): submits a request stream with
-Poisson arrivals and collects latency / throughput.  Argument marshalling and
+Poisson arrivals and collects latency / throughput, and runs loading curves
+with and without server sessions.  Argument marshalling and
 timing only; every solve runs in the library.
 
     python -m paper_1612_08395_amd.serving --requests 10000 --out stream.json
@@ -58,6 +59,54 @@ def run_stream(requests, precision, qps=None, n_slots=4, budget_bytes=8 << 30, s
     if want_p:
         st["results"] = [(p[0], p[1], p[2], p[3]) for p in polled]
     return st
+
+
+def curve_steps(r, steps=8):
+    """The indentation steps of one request's loading curve: `steps` loading
+    steps up to its depth d, or, for an adhesive request (gamma > 0), half as
+    many loading steps up to d_preload and as many pull-off steps down from
+    it.  Returns [(d, adhesive), ...]."""
+    if r["gamma"] > 0:
+        m = steps // 2
+        d0 = r["d_preload"]
+        return ([(d0 * (j + 1) / m, False) for j in range(m)] +
+                [(d0 * (m - 1 - j) / m, True) for j in range(m)])
+    return [(r["d"] * (j + 1) / steps, False) for j in range(steps)]
+
+
+def run_curves(requests, precision, sessions, steps=8, n_slots=4, budget_bytes=8 << 30,
+               batch_slots=16, nu=0.3):
+    """Each request becomes a load(-unload) curve (curve_steps), all curves
+    submitted at once.  sessions=True: one server session per curve, so each
+    step starts from the previous step's state on the device; False: every
+    step an independent request (cold start; a pull-off step then makes its
+    contact set by a non-adhesive preload to the curve's deepest step, as a
+    client without sessions would have to).  Returns a dict of statistics."""
+    srv = bem.bem_server_create_ex(budget_bytes, n_slots, batch_slots)
+    t0 = time.perf_counter()
+    ids = []
+    for r in requests:
+        sid = srv.session_open() if sessions else None
+        cs = curve_steps(r, steps)
+        dmax = max(d for d, _ in cs)
+        for d, adh in cs:
+            prm = bem.bem_params_init(d=d, gamma=r["gamma"] if adh else 0.0,
+                                      d_preload=0.0 if sessions else dmax, precision=precision)
+            ids.append(srv.submit(r["n"], r["n"], 1.0 / r["n"], r["k"], nu, r["h"], prm,
+                                  session=sid))
+        if sessions:
+            srv.session_close(sid)   # no more requests; released after its last one
+    polled = [srv.poll(i) for i in ids]
+    t1 = time.perf_counter()
+    st = srv.stats().as_dict()
+    srv.free()
+    iters = [p[1].iters for p in polled]
+    statuses = [p[0] for p in polled]
+    return {"curves": len(requests), "solves": len(ids), "wall_s": t1 - t0,
+            "solves_per_s": len(ids) / (t1 - t0), "mean_iters": float(np.mean(iters)),
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "batched": st["batched"],
+            "status_counts": {int(x): statuses.count(x) for x in set(statuses)}}
 
 
 KEYS_SAT = ("solves_per_s", "p50_latency_s", "p99_latency_s", "mean_wait_s", "peak_running",

@@ -172,3 +172,118 @@ def test_admission_under_a_tight_budget():
                    bem.bem_params_init(d=0.005))
     assert e.value.code == bem.BEM_ENOMEM
     srv.free()
+
+
+def _session_curve(bem, srv, sid, n, k, h, steps, prec, gam):
+    # the steps of a load-unload curve as requests of one session: loading
+    # steps non-adhesive, pull-off steps (below the previous step) adhesive
+    ids, prev = [], None
+    for d in steps:
+        unloading = gam > 0 and prev is not None and d < prev
+        prm = bem.bem_params_init(d=d, gamma=gam if unloading else 0.0, precision=prec)
+        ids.append(srv.submit(n, n, 1.0 / n, k, 0.3, h, prm, want_p=True, session=sid))
+        prev = d
+    return ids
+
+
+@pytest.mark.parametrize("n,k,prec,adhesive", [
+    (64, 0.3, "fp64", False), (96, -0.4, "mixed", False), (64, 0.5, "fp64", True),
+    (128, 0.0, "mixed", True)])
+def test_session_requests_are_the_steps_of_bem_sweep(n, k, prec, adhesive):
+    # one session's requests on one gap profile run as the steps of bem_sweep
+    # (warm start from the previous pressure and contact set, iteration 0 from
+    # the previous gap shifted): the same forces, iteration counts, detach
+    # rounds and final pressure, bitwise, while other clients' requests run
+    from paper_1612_08395_amd import bem
+    announce("server-session", n, k, prec, adhesive)
+    P = bem.BEM_FP64 if prec == "fp64" else bem.BEM_MIXED
+    h = inputs.parabolic(n, 1.0, 1.0)
+    d3 = 0.15 ** 2 / (1 + k)
+    gam = float(np.sqrt(125.0 * (1 / (1 - 0.09)) ** 2 / n ** 3)) if adhesive else 0.0
+    steps = [d3 / 3, 2 * d3 / 3, d3, d3 / 2, 0.0] if adhesive else [d3 / 4, d3 / 2, d3, 1.5 * d3]
+    srv = bem.bem_server_create_ex(budget_bytes=4 << 30, n_slots=4, batch_slots=16)
+    sid = srv.session_open()
+    ids = _session_curve(bem, srv, sid, n, k, h, steps, P, gam)
+    others = [srv.submit(m, m, 1.0 / m, kk, 0.3, hh, pp, want_p=True)
+              for (m, kk, hh, pp) in _mix(bem, np.random.default_rng(11), 8)]
+    got = [srv.poll(i) for i in ids]
+    for i in others:
+        assert srv.poll(i)[0] >= 0
+    srv.session_close(sid)
+    st = srv.stats()
+    srv.free()
+    assert st.failed == 0 and st.device_bytes_reserved <= 4 << 30
+    K = bem.bem_influence(n, n, 1.0 / n, k, 0.3)
+    S = bem.bem_state_create(K)
+    rc, res = bem.bem_sweep(K, h, bem.bem_params_init(gamma=gam, precision=P), steps, state=S)
+    p_last, _ = bem.bem_state_get(S)
+    S.free()
+    K.free()
+    for (status, r, p, c), ra in zip(got, res):
+        assert status >= 0
+        assert r.F == ra.F and r.iters == ra.iters and r.n_contact == ra.n_contact
+        assert r.detach_rounds == ra.detach_rounds and r.residual == ra.residual
+    assert np.array_equal(got[-1][2], p_last)
+    print(f"[server-session] iterations per step {[r.iters for _, r, _, _ in got]}", flush=True)
+
+
+def test_session_with_new_profile_warm_starts_to_the_same_solution():
+    # a request whose gap profile differs from the session's previous one
+    # starts from the previous pressure only; a non-adhesive solution is
+    # unique, so it matches a cold solve to the CG tolerance
+    from paper_1612_08395_amd import bem
+    announce("server-session new profile")
+    n, k = 96, 0.2
+    h1 = inputs.parabolic(n, 1.0, 1.0)
+    h2 = inputs.fractal_gap(n, 1.0, 0.7, 8 * 2 * np.pi, n / 4 * 2 * np.pi, 1e-3, 77) + h1
+    d = 0.01
+    srv = bem.bem_server_create_ex(budget_bytes=1 << 30, n_slots=2, batch_slots=0)
+    sid = srv.session_open()
+    prm = bem.bem_params_init(d=d)
+    i1 = srv.submit(n, n, 1.0 / n, k, 0.3, h1, prm, want_p=True, session=sid)
+    i2 = srv.submit(n, n, 1.0 / n, k, 0.3, h2, prm, want_p=True, session=sid)
+    (_, r1, _, _), (s2, r2, p2, c2) = srv.poll(i1), srv.poll(i2)
+    srv.session_close(sid)
+    srv.free()
+    K = bem.bem_influence(n, n, 1.0 / n, k, 0.3)
+    rc, ra, pa, ca, _ = bem.bem_solve(K, h2, prm)
+    K.free()
+    assert s2 == rc == bem.BEM_OK
+    assert np.linalg.norm(p2 - pa) <= 1e-8 * np.linalg.norm(pa)
+    assert abs(r2.F - ra.F) <= 1e-10 * abs(ra.F)
+    assert np.array_equal(c2, ca)
+
+
+def test_session_errors_and_budget():
+    from paper_1612_08395_amd import bem
+    announce("server-session errors")
+    n = 64
+    h = inputs.parabolic(n, 1.0, 1.0)
+    prm = bem.bem_params_init(d=0.005, precision=bem.BEM_MIXED)
+    srv = bem.bem_server_create_ex(budget_bytes=1 << 30, n_slots=2, batch_slots=16)
+    sid = srv.session_open()
+    i1 = srv.submit(n, n, 1.0 / n, 0.3, 0.3, h, prm, session=sid)
+    for bad in ((n + 1, 0.3, bem.BEM_MIXED), (n, 0.2, bem.BEM_MIXED), (n, 0.3, bem.BEM_FP64)):
+        m, kk, pr = bad
+        with pytest.raises(bem.BemError) as e:
+            srv.submit(m, m, 1.0 / n, kk, 0.3, inputs.parabolic(m, 1.0, 1.0),
+                       bem.bem_params_init(d=0.005, precision=pr), session=sid)
+        assert e.value.code == bem.BEM_EINVAL
+    assert srv.poll(i1)[0] == bem.BEM_OK
+    reserved_open = srv.stats().device_bytes_reserved
+    srv.session_close(sid)
+    with pytest.raises(bem.BemError):
+        srv.session_close(sid)
+    with pytest.raises(bem.BemError):
+        srv.submit(n, n, 1.0 / n, 0.3, 0.3, h, prm, session=sid)
+    with pytest.raises(bem.BemError):
+        srv.submit(n, n, 1.0 / n, 0.3, 0.3, h, prm, session=12345)
+    # the closed session's state went back to the pool: the same grid runs on
+    # the per-request path without reserving more memory
+    sid2 = srv.session_open()
+    i2 = srv.submit(n, n, 1.0 / n, 0.3, 0.3, h, prm, session=sid2)
+    assert srv.poll(i2)[0] == bem.BEM_OK
+    st = srv.stats()
+    assert st.device_bytes_reserved == reserved_open and st.cache_hits >= 1
+    srv.session_close(sid2)
+    srv.free()
