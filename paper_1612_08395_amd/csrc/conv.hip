@@ -10,11 +10,17 @@
 
 namespace bem {
 
+// One column per workgroup by default: more, smaller workgroups share each
+// CU and do not load, transform and store in step.  Measured against the
+// widest group the LDS allowed (FP64 at 2048^2: 2 columns; FP32 and FP64 at
+// 1024^2: 4): column sweep FP64 2048^2 99.3 -> 83.7 us, 1024^2 27.0 -> 20.9
+// us, FP32 1024^2 17.7 -> 16.6 us; spectral energy FP64 2048^2 65.5 -> 58.9
+// us; the FP64 2048^2 sweep 60.5 -> 65.9 solves/s.
 int col_width_cap() {
   static const int cap = [] {
     const char* v = getenv("BEM_COL_WIDTH");
-    const int c = v ? atoi(v) : 16;
-    return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 16;
+    const int c = v ? atoi(v) : 1;
+    return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) ? c : 1;
   }();
   return cap;
 }

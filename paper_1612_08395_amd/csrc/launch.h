@@ -42,7 +42,8 @@ __host__ __device__ constexpr int col_width_lds(int LY) {
   return w;
 }
 
-// Tuning knob: BEM_COL_WIDTH (1, 2, 4, 8, 16) caps the column-group width.
+// Tuning knob: BEM_COL_WIDTH (1 = default, 2, 4, 8, 16) caps the column-group
+// width of the LDS Stockham column kernels.
 int col_width_cap();
 
 // Tuning knob BEM_ROW_WAVE: 1 (default) = wave-FFT row sweeps for FP32 at
