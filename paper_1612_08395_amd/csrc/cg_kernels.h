@@ -731,9 +731,7 @@ __global__ __launch_bounds__(EW_THREADS) void k_finalize(T* __restrict__ p,
   __shared__ double red[64];
   double sp = 0.0, nc = 0.0, npen = 0.0;
   const double scale = FC ? sc->scale : 1.0;
-  for (size_t i = blockIdx.x * (size_t)EW_THREADS + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * EW_THREADS) {
-    T pv = p[i];
+  auto elem = [&](size_t i, T pv, bool m, T gv) {
     if constexpr (FC) {
       // load control: apply the scale of the stopping iteration
       pv = (T)(scale * (double)pv);
@@ -742,14 +740,32 @@ __global__ __launch_bounds__(EW_THREADS) void k_finalize(T* __restrict__ p,
     sp += (double)pv;
     bool in;
     if constexpr (FS) {
-      in = mask[i] != 0;
-      if (!in && g[i] < T(0)) npen += 1.0;
+      in = m;
+      if (!in && gv < T(0)) npen += 1.0;
     } else {
       in = pv > T(0);
       mask[i] = in ? 1 : 0;
     }
     nc += in ? 1.0 : 0.0;
+  };
+  // U elements per thread in flight at once (their loads first), visited in
+  // the order of the plain grid-stride loop, so the sums are the same
+  constexpr int U = 4;
+  const size_t stride = (size_t)gridDim.x * EW_THREADS;
+  size_t i = blockIdx.x * (size_t)EW_THREADS + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    T pv[U], gv[U];
+    bool mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pv[u] = p[i + u * stride];
+      mv[u] = FS ? mask[i + u * stride] != 0 : false;
+      gv[u] = FS ? g[i + u * stride] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) elem(i + u * stride, pv[u], mv[u], gv[u]);
   }
+  for (; i < n; i += stride) elem(i, p[i], FS ? mask[i] != 0 : false, FS ? g[i] : T(0));
   const double acc[3] = {sp, nc, npen};
   double tot[3];
   if (grid_reduce_last<3, EW_THREADS>(acc, red, part + kPartElem, &sc->ticket[3], tot) && threadIdx.x == 0) {
