@@ -251,7 +251,7 @@ def cpu_baseline(h, depths, iters_per_solve, sample_iters):
                        f"{cores} workers) at 2048^2, depth d10, {t:.1f} s; scaled by the GPU "
                        f"FP64 mean of {iters_per_solve:.1f} iterations/solve; influence "
                        f"setup {t_setup:.1f} s not counted"),
-            "s_per_iter": round(per_iter, 4), "units": oracle_units(cores, Kq)}
+            "s_per_iter": round(per_iter, 4), "units": oracle_units(cores, Kq, h, depths)}
 
 
 # Depth of 10 % contact area of the 4096^2 workload, by bisection on the
@@ -431,10 +431,15 @@ def adhesive_4096(bem, torch, n_load=10, n_unload=10):
     return out
 
 
-def oracle_units(cores, Kq):
+def oracle_units(cores, Kq, h=None, depths=None):
     """Further oracle timings (FP64 numpy / scipy.fft): one 2048^2
-    convolution on `cores` workers and on one, and the 128^2 Hertz-type
-    solve (k = 0.5, nu = 0.3, R = 1, side 2, d = 0.01, tol 1e-12)."""
+    convolution on `cores` workers and on one; the 128^2 Hertz-type solve
+    (k = 0.5, nu = 0.3, R = 1, side 2, d = 0.01, tol 1e-12); one pull-off
+    step of the 512^2 adhesive example (k = 0, gamma = 2.9995e-3, preload to
+    (1.5 a_F)^2 / R untimed, then the step at half that depth); one 256^2
+    window of the 4096^2 surface (k = -0.3, nu = 0.25, 10 % height quantile);
+    and step 5 of the 20-step 2048^2 sweep, cold started (the deepest step
+    is the sampled iterations scaled, see cpu_baseline)."""
     from oracle import influence as inf
     from oracle import material as m
     from oracle import solver as so
@@ -455,6 +460,41 @@ def oracle_units(cores, Kq):
     t0 = time.perf_counter()
     so.solve_nonadhesive(Kq1, m.compliance(0.5, 0.3), h1, 0.01, tol=1e-12)
     out["solve_128_hertz_s"] = round(time.perf_counter() - t0, 4)
+    # 512^2 adhesive example: preload (untimed), then one pull-off step
+    n2, L2, gam = 512, 2.0, 2.9995e-3
+    dx2 = L2 / n2
+    Kq2 = inf.influence_quarter(n2, n2, dx2, dx2, 0.0)
+    C2 = m.compliance(0.0, 0.3)
+    conv2 = FFTConvolver(Kq2, C2, workers=cores)
+    h2 = inputs.parabolic(n2, L2, 1.0)
+    d0 = (1.5 * 0.213) ** 2
+    pre = so.solve_nonadhesive(Kq2, C2, h2, d0, tol=1e-12, conv=conv2)
+    t0 = time.perf_counter()
+    so.adhesive_step(Kq2, C2, h2, 0.5 * d0, pre.p > 0, pre.p,
+                     m.p_crit(0.0, 0.3, gam, dx2), tol=1e-12, conv=conv2)
+    out["adhesive_step_512_s"] = round(time.perf_counter() - t0, 4)
+    # a 256^2 window of the 4096^2 surface
+    n4, w = 4096, 256
+    h4 = inputs.fractal_gap(n4, L, H_EXP, Q0 * 2 * math.pi / L, Q1 * 2 * math.pi / L, RMS * L,
+                            8395)
+    hw = h4[n4 // 4 - w // 2: n4 // 4 + w // 2, n4 // 4 - w // 2: n4 // 4 + w // 2].copy()
+    del h4
+    hw -= hw.min()
+    Kq4 = inf.influence_quarter(w, w, L / n4, L / n4, -0.3)
+    t0 = time.perf_counter()
+    so.solve_nonadhesive(Kq4, m.compliance(-0.3, 0.25), hw, float(np.quantile(hw, 0.1)),
+                         tol=1e-12, conv=FFTConvolver(Kq4, m.compliance(-0.3, 0.25),
+                                                      workers=cores))
+    out["crop_256_solve_s"] = round(time.perf_counter() - t0, 4)
+    # a step of the 2048^2 sweep, solved from a cold start
+    if h is not None and depths is not None:
+        conv = FFTConvolver(Kq, m.compliance(K_EXP, NU), workers=cores)
+        for s_i in (5,):
+            t0 = time.perf_counter()
+            r = so.solve_nonadhesive(Kq, m.compliance(K_EXP, NU), h, depths[s_i - 1], tol=1e-12,
+                                     conv=conv)
+            out[f"solve_2048_step{s_i}_s"] = round(time.perf_counter() - t0, 3)
+            out[f"solve_2048_step{s_i}_iters"] = int(r.iters)
     return out
 
 
