@@ -504,7 +504,8 @@ def serving(count, slots, bem):
     with continuous batching (16 slots per geometry class), then Poisson
     arrivals at 0.8 x the FP64 saturation rate for both paths; the MIXED
     saturation run once more without batching (every request a solve of its
-    own) for comparison; and the requests the MIXED path stopped at its
+    own) and with continuous k (no influence operator reused) for
+    comparison; and the requests the MIXED path stopped at its
     rounding floor (BEM_EFLOOR), solved alone in both precisions, with their
     pressure difference; then loading curves of 40 of the requests with and
     without server sessions (serving.run_curves)."""
@@ -522,6 +523,10 @@ def serving(count, slots, bem):
             floor_idx = [j for j, st in enumerate(s["statuses"]) if st == bem.BEM_EFLOOR]
     s = run_stream(reqs, bem.BEM_MIXED, None, slots, batch_slots=0)
     out["mixed_saturation_unbatched"] = {k: s[k] for k in KEYS_SAT}
+    # the same stream with continuous k: every request builds its influence
+    s = run_stream(inputs.serving_requests(count, 2024, continuous_k=True), bem.BEM_MIXED, None,
+                   slots)
+    out["mixed_saturation_continuous_k"] = {k: s[k] for k in KEYS_SAT}
     qps = 0.8 * sat["fp64"]
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
         s = run_stream(reqs, prec, qps, slots, seed=7)

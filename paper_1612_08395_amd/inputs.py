@@ -100,7 +100,7 @@ def random_pressure(n_y, n_x, seed, scale=1.0):
     return scale * rng.random((n_y, n_x))
 
 
-def serving_requests(count, seed, nu=0.3, mu_tabor=5.0):
+def serving_requests(count, seed, nu=0.3, mu_tabor=5.0, continuous_k=False):
     """A stream of independent solve requests of mixed size, material and
     indenter (all seeded):
 
@@ -117,9 +117,13 @@ def serving_requests(count, seed, nu=0.3, mu_tabor=5.0):
       parameter mu = (R gamma^2 / (E*^2 dx^3))^(1/3) = 5 with R = 1 and the
       grid spacing as interaction range; non-adhesive preload to d0, then one
       pull-off solve at d0 / 2.
+    continuous_k: the same stream with every k moved by U(-0.025, 0.025)
+    (drawn from a generator of its own, so that the other draws are those of
+    the 0.05-grid stream): no two requests share an influence operator.
     Returns a list of dicts (n, k, shape, h, d, d_preload, gamma).
     """
     rng = np.random.default_rng(seed)
+    rng_k = np.random.default_rng(seed + 1)
     ks = np.round(np.arange(-15, 16) * 0.05, 10)
     estar = 1.0 / (1.0 - nu * nu)
     surfaces = {}
@@ -128,6 +132,8 @@ def serving_requests(count, seed, nu=0.3, mu_tabor=5.0):
         n = int(round(2.0 ** rng.uniform(6.0, 10.0) / 16.0)) * 16
         n = max(64, min(1024, n))
         k = float(rng.choice(ks))
+        if continuous_k:
+            k = float(np.clip(k + rng_k.uniform(-0.025, 0.025), -0.795, 0.795))
         shape = ["parabolic", "cone", "punch", "rough"][int(rng.integers(0, 4))]
         L = 1.0
         if shape == "parabolic":

@@ -127,15 +127,17 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--phase", choices=("all", "saturation", "poisson"), default="all",
                     help="saturation runs, Poisson runs (needs --qps), or both")
+    ap.add_argument("--continuous-k", action="store_true",
+                    help="k off the 0.05 grid: every request builds its influence operator")
     ap.add_argument("--qps", type=float, default=None,
                     help="Poisson arrival rate (default: 0.8 x the FP64 saturation rate)")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    reqs = inputs.serving_requests(a.requests, a.seed)
+    reqs = inputs.serving_requests(a.requests, a.seed, continuous_k=a.continuous_k)
     print(f"[serving] {len(reqs)} requests built", file=sys.stderr, flush=True)
     budget = int(a.budget_gb * (1 << 30))
-    out = {"requests": a.requests, "seed": a.seed, "slots": a.slots,
+    out = {"requests": a.requests, "seed": a.seed, "continuous_k": a.continuous_k, "slots": a.slots,
            "batch_slots": a.batch_slots, "budget_bytes": budget}
     sat = {}
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
