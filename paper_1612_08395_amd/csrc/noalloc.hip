@@ -14,13 +14,14 @@
 #include "../../include/bem.h"
 #include "internal.h"
 
-namespace bem {
-namespace {
-
 static_assert(BEM_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
 
-// Row spectrum of the allocation-free convolution (ny x Lx complex values).
-__device__ __align__(256) unsigned char scratch[BEM_NOALLOC_SCRATCH_BYTES];
+// Row spectrum of the allocation-free convolution (spec_rows(ny) x Lx complex
+// values); one copy per device, for the life of the process.
+static __device__ __align__(256) unsigned char scratch[BEM_NOALLOC_SCRATCH_BYTES];
+
+namespace bem {
+namespace {
 
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
