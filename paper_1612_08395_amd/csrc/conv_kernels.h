@@ -12,7 +12,8 @@
 //    w = exp(-2 pi i / Mx)).  The real-row spectra A, B (bins 0..Lx) are
 //    untangled from Z[k] and conj(Z[Mx - k]).  Bins 0 and Lx of a real row
 //    are real, so slot 0 stores (A[0], A[Lx]): the spectrum S has exactly
-//    Lx complex columns and row pitch Lx.
+//    Lx complex columns, its row pairs interleaved per column (spec_idx in
+//    common.h).
 //  * column sweep: for each spectrum column, the My-point DFT of the ny
 //    non-zero values (same even/odd split), multiplication by the real,
 //    even kernel spectrum, inverse DFT, and only outputs y < ny kept

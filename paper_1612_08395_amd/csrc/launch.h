@@ -10,8 +10,8 @@
 namespace bem {
 
 // Problem geometry.  Mx = 2 Lx, My = 2 Ly (powers of two); the row spectrum
-// has ny rows of Lx complex values; the kernel spectrum has Lx + 1 rows of
-// kpitch reals (ky in [0, Ly]).
+// has ny rows of Lx complex values (row pairs interleaved, spec_idx); the
+// kernel spectrum has Lx + 1 rows of kpitch reals (ky in [0, Ly]).
 struct Geom {
   int nx, ny, Lx, Ly, kpitch;
 };
