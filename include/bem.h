@@ -345,14 +345,15 @@ int bem_server_submit(bem_server_t srv, const bem_request* req, long long* id);
  * client that solves one indenter through a sequence of loads (a loading /
  * unloading curve, Section 3.1) opens a session and submits its requests to
  * it.  The server keeps one solver state for the session between its
- * requests and runs them one at a time, in submission order, on the
- * per-request path: each starts from the previous request's pressure and
- * contact set (the warm start of bem_solve with a state), and, when its gap
- * profile is the same as the previous request's, from that request's gap
- * shifted to the new indentation, exactly as the steps of bem_sweep (a
- * sequence of requests then gives bem_sweep's results bitwise).  Loading
- * steps are non-adhesive requests; pull-off steps are adhesive requests,
- * which hold the state's contact set fixed (bem_solve).
+ * requests and runs them one at a time, in submission order: each starts
+ * from the previous request's pressure and contact set.  On the batched path
+ * (see bem_server_create_ex) a request is then exactly bem_solve with that
+ * state; on the per-request path a request whose gap profile is the same as
+ * the previous request's also starts from that request's gap shifted to the
+ * new indentation, exactly as the steps of bem_sweep.  Either way the
+ * results are bitwise those of the corresponding library calls on one
+ * state.  Loading steps are non-adhesive requests; pull-off steps are
+ * adhesive requests, which hold the state's contact set fixed (bem_solve).
  *
  * bem_server_session_open: *session identifies the new session (> 0).
  * bem_server_submit_session: as bem_server_submit; the first request fixes

@@ -22,10 +22,11 @@
 //
 // Sessions: a client that solves one indenter through a sequence of loads
 // opens a session; the server keeps one solver state on the device for it
-// between its requests (per-request path, one at a time, in submission
-// order), so each request starts from the previous one's pressure and
-// contact set, and from its gap when the profile is the same (a step of a
-// sweep, as in bem_sweep).
+// between its requests (one at a time, in submission order), so each request
+// starts from the previous one's pressure and contact set: on the batched
+// path as bem_solve with that state, on the per-request path also from the
+// previous gap when the profile is the same (a step of a sweep, as in
+// bem_sweep).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -216,7 +217,12 @@ void release_session_locked(bem_server_s* S, Session* ss);
 
 void complete_locked(bem_server_s* S, Req* r, Entry* e, bem_state_t state, int rc) {
   if (Session* ss = r->session) {
-    // the session keeps the state and its hold on the entry
+    // the session keeps the state and its hold on the entry; after a failed
+    // request its next one starts cold
+    if (rc < 0) {
+      if (state) bem_state_reset(state);
+      ss->h_prev.clear();
+    }
     ss->st = state;
     ss->busy = false;
     ss->pending--;
@@ -399,13 +405,25 @@ int slot_setup(Runner* R, int i) {
   sl.iters = sl.rounds = 0;
   sl.resid = 0.0;
   bem_state_s* st = sl.st;
-  // a cold adhesive solve first makes its contact set non-adhesively at
-  // max(d, d_preload) (Section 3.1)
-  const double d0 = sl.adhesive ? std::max(P.d, P.d_preload) : P.d;
-  hipError_t e = launch_make_hd<T>(st->h64, d0, (T*)st->hd, st->n, R->stream);
-  if (e == hipSuccess)
-    e = launch_cold_start<T>((T*)st->p, (const T*)st->hd, 1.0 / (K->C * K->K00), st->n, R->stream);
-  if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_DISP);
+  st->g_valid = false;   // the batched kernels do not start from a shifted gap
+  hipError_t e;
+  if (sl.adhesive && st->has_mask) {
+    // a pull-off step on the contact set the state holds (a session's
+    // previous request): fixed-set solves at d at once
+    e = launch_make_hd<T>(st->h64, P.d, (T*)st->hd, st->n, R->stream);
+    if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_FIXED);
+  } else {
+    // an adhesive solve without a contact set first makes one non-adhesively
+    // at max(d, d_preload) (Section 3.1); a state with a pressure (a
+    // session's previous request) starts from it, else cold
+    const double d0 = sl.adhesive ? std::max(P.d, P.d_preload) : P.d;
+    e = launch_make_hd<T>(st->h64, d0, (T*)st->hd, st->n, R->stream);
+    if (e == hipSuccess && !st->has_p)
+      e = launch_cold_start<T>((T*)st->p, (const T*)st->hd, 1.0 / (K->C * K->K00), st->n,
+                               R->stream);
+    st->has_p = true;
+    if (e == hipSuccess) e = slot_start_cg<T>(R, i, CG_DISP);
+  }
   if (e != hipSuccess) return hip_fail(e, "batched solve setup");
   return BEM_OK;
 }
@@ -415,20 +433,31 @@ int slot_setup(Runner* R, int i) {
 // device.  Then the request joins its runner's ready list, or fails.
 void prepare_batched(bem_server_s* S, Runner* R, Req* r, hipStream_t s) {
   Entry* e = r->entry;
-  bem_state_t state = r->lent;
+  Session* ss = r->session;
+  // a session's state keeps its warm-start data; any other starts cold
+  bem_state_t state = ss ? ss->st : r->lent;
   int rc = entry_influence(S, r, e);
   for (double v : r->h)
     if (rc == BEM_OK && !is_finite(v)) rc = set_error(BEM_EINVAL, "bem_solve: non-finite gap profile");
   if (rc == BEM_OK && !state) rc = bem_state_create(e->K, &state);
   if (rc == BEM_OK) {
-    bem_state_reset(state);
+    if (!ss) bem_state_reset(state);
     rc = ensure_precision(state, R->prec, s);
   }
-  if (rc == BEM_OK) {
+  const bool same_h = ss && !ss->h_prev.empty() && ss->h_prev == r->h;
+  if (rc == BEM_OK && !same_h) {
     hipError_t he = hipMemcpyAsync(state->h64, r->h.data(), state->n * sizeof(double),
                                    hipMemcpyHostToDevice, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) rc = hip_fail(he, "gap profile upload");
+  }
+  if (ss) {
+    if (rc == BEM_OK) {
+      if (!same_h) ss->h_prev = r->h;
+    } else {
+      if (state) bem_state_reset(state);   // the next request starts cold
+      ss->h_prev.clear();
+    }
   }
   std::unique_lock<std::mutex> lk(S->mu);
   R->preparing--;
@@ -460,6 +489,8 @@ hipError_t slot_outputs(Runner* R, int i) {
   res.iters = sl.iters;
   res.detach_rounds = sl.rounds;
   res.status = sl.status;
+  // a solve that ends with no pressure anywhere leaves nothing to warm-start from
+  if (h->fin_contact == 0.0) st->has_p = false;
   hipError_t e = hipSuccess;
   const size_t n = st->n;
   if (r->r.p_out) {
@@ -515,6 +546,7 @@ hipError_t slot_advance(Runner* R, int i, int chunk, std::vector<std::pair<int, 
       sl.mode = BATCH_EMPTY;
       break;
     case PH_FIN_DISP:
+      sl.st->has_mask = true;   // the contact set {p > 0} the final sums wrote
       if (sl.adhesive) {
         // the pull-off step: fixed-set solves at d on the preload's contact set
         e = launch_make_hd<T>(sl.st->h64, sl.r->r.prm.d, (T*)sl.st->hd, sl.st->n, R->stream);
@@ -744,6 +776,34 @@ bool batch_class(const bem_server_s* S, const bem_request& q, ClassKey* key) {
   return true;
 }
 
+// The first request of `q` that can start now (lock held): requests start in
+// queue order, except that one whose session is still busy with its
+// predecessor is passed over; a session's later requests need no admission
+// (its first one holds the entry and the state).  Returns nullptr when the
+// first candidate does not fit the budget yet, so memory admission keeps the
+// queue's order.
+Req* take_startable(bem_server_s* S, std::deque<Req*>& q, Entry** entry) {
+  for (auto qi = q.begin(); qi != q.end(); ++qi) {
+    Req* c = *qi;
+    Session* ss = c->session;
+    if (ss && ss->busy) continue;
+    Entry* ce = (ss && ss->e) ? ss->e : admit(S, c);
+    if (!ce) return nullptr;
+    if (ss) {
+      ss->busy = true;
+      if (!ss->e) {   // the session's first request: its admission is the session's
+        ss->e = ce;
+        ss->st = c->lent;
+        c->lent = nullptr;
+      }
+    }
+    q.erase(qi);
+    *entry = ce;
+    return c;
+  }
+  return nullptr;
+}
+
 void worker(bem_server_s* S, int slot) {
   (void)hipSetDevice(S->device);
   hipStream_t st = S->streams[slot];
@@ -761,37 +821,16 @@ void worker(bem_server_s* S, int slot) {
           Runner* R = kv.second;
           if (R->queue.empty() || R->active + (int)R->ready.size() + R->preparing >= R->nslots)
             continue;
-          e = admit(S, R->queue.front());
-          if (!e) continue;
-          r = R->queue.front();
-          R->queue.pop_front();
+          r = take_startable(S, R->queue, &e);
+          if (!r) continue;
           r->entry = e;
           R->preparing++;
           prep = R;
           break;
         }
         if (r) break;
-        // per-request path, in submission order; a request whose session is
-        // busy waits for its predecessor without holding up the others
-        for (auto qi = S->queue.begin(); qi != S->queue.end(); ++qi) {
-          Req* c = *qi;
-          Session* ss = c->session;
-          if (ss && ss->busy) continue;
-          Entry* ce = (ss && ss->e) ? ss->e : admit(S, c);
-          if (!ce) break;   // memory: admission keeps the queue's order
-          if (ss) {
-            ss->busy = true;
-            if (!ss->e) {   // the session's first request: its admission is the session's
-              ss->e = ce;
-              ss->st = c->lent;
-              c->lent = nullptr;
-            }
-          }
-          e = ce;
-          r = c;
-          S->queue.erase(qi);
-          break;
-        }
+        // per-request path, in submission order
+        r = take_startable(S, S->queue, &e);
         if (r) break;
         S->cv_work.wait(lk);
       }
@@ -934,11 +973,10 @@ static int submit_impl(bem_server_t S, long long session, const bem_request* req
     return set_error(BEM_ENOMEM, "bem_server_submit: request needs %lld bytes, budget %lld",
                      fi + fs, S->budget);
   }
-  // the batched path: the runner of the request's class (made on first use);
-  // a session's requests stay on the per-request path
+  // the batched path: the runner of the request's class (made on first use)
   ClassKey key;
   Runner* R = nullptr;
-  if (session == 0 && batch_class(S, q, &key)) {
+  if (batch_class(S, q, &key)) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       auto it = S->runners.find(key);

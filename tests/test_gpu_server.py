@@ -188,12 +188,14 @@ def _session_curve(bem, srv, sid, n, k, h, steps, prec, gam):
 
 @pytest.mark.parametrize("n,k,prec,adhesive", [
     (64, 0.3, "fp64", False), (96, -0.4, "mixed", False), (64, 0.5, "fp64", True),
-    (128, 0.0, "mixed", True)])
-def test_session_requests_are_the_steps_of_bem_sweep(n, k, prec, adhesive):
-    # one session's requests on one gap profile run as the steps of bem_sweep
-    # (warm start from the previous pressure and contact set, iteration 0 from
-    # the previous gap shifted): the same forces, iteration counts, detach
-    # rounds and final pressure, bitwise, while other clients' requests run
+    (128, 0.0, "mixed", True), (288, 0.2, "mixed", False), (320, 0.5, "fp64", True)])
+def test_session_requests_match_the_library_on_one_state(n, k, prec, adhesive):
+    # one session's requests on one gap profile, while other clients'
+    # requests run: grids up to 256^2 take the batched path, where each
+    # request is bem_solve with the session's state; larger ones the
+    # per-request path, where they are the steps of bem_sweep (iteration 0
+    # from the previous gap shifted).  Forces, iteration counts, detach
+    # rounds and the final pressure agree bitwise with those calls.
     from paper_1612_08395_amd import bem
     announce("server-session", n, k, prec, adhesive)
     P = bem.BEM_FP64 if prec == "fp64" else bem.BEM_MIXED
@@ -213,9 +215,20 @@ def test_session_requests_are_the_steps_of_bem_sweep(n, k, prec, adhesive):
     st = srv.stats()
     srv.free()
     assert st.failed == 0 and st.device_bytes_reserved <= 4 << 30
+    batched = n <= 256
+    assert st.batched >= (len(steps) if batched else 0)
     K = bem.bem_influence(n, n, 1.0 / n, k, 0.3)
     S = bem.bem_state_create(K)
-    rc, res = bem.bem_sweep(K, h, bem.bem_params_init(gamma=gam, precision=P), steps, state=S)
+    if batched:
+        res, prev = [], None
+        for d in steps:
+            unloading = gam > 0 and prev is not None and d < prev
+            prm = bem.bem_params_init(d=d, gamma=gam if unloading else 0.0, precision=P)
+            res.append(bem.bem_solve(K, h, prm, state=S)[1])
+            prev = d
+    else:
+        rc, res = bem.bem_sweep(K, h, bem.bem_params_init(gamma=gam, precision=P), steps,
+                                state=S)
     p_last, _ = bem.bem_state_get(S)
     S.free()
     K.free()
