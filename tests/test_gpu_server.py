@@ -300,3 +300,21 @@ def test_session_errors_and_budget():
     assert st.device_bytes_reserved == reserved_open and st.cache_hits >= 1
     srv.session_close(sid2)
     srv.free()
+
+
+def test_server_free_with_open_sessions_and_queued_requests():
+    # freeing the server drops queued requests and returns every session's
+    # state, whether its requests ran or not
+    from paper_1612_08395_amd import bem
+    announce("server-session free")
+    srv = bem.bem_server_create_ex(budget_bytes=1 << 30, n_slots=2, batch_slots=16)
+    sids = [srv.session_open() for _ in range(3)]
+    for j, (n, k) in enumerate(((64, 0.3), (320, 0.1), (128, -0.2))):
+        h = inputs.parabolic(n, 1.0, 1.0)
+        for d in (0.002, 0.004, 0.006):
+            srv.submit(n, n, 1.0 / n, k, 0.3, h, bem.bem_params_init(d=d), session=sids[j])
+    first = srv.submit(64, 64, 1.0 / 64, 0.3, 0.3, inputs.parabolic(64, 1.0, 1.0),
+                       bem.bem_params_init(d=0.003))
+    assert srv.poll(first)[0] == bem.BEM_OK
+    srv.session_close(sids[0])
+    srv.free()                                   # sessions 1 and 2 still open
