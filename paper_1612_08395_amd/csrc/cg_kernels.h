@@ -182,7 +182,7 @@ struct UpdatePro {
   static constexpr bool FS = MODE == CG_FIXED, FC = MODE == CG_FORCE;
   static constexpr int NVD = FC ? 4 : 1;
   T* p;
-  const T* t;
+  T* t;                  // read on Ic; zeroed where an element leaves Ic
   const T* g;
   uint8_t* mask;         // fixed set: the set A (read); else Ic = {p > 0} (written)
   const CgScal* sc;
@@ -310,6 +310,10 @@ struct UpdatePro {
           // contact flags for the rest of the iteration (1 byte instead of p)
           mask[(size_t)ya * nx + n] = va[q] > T(0) ? 1 : 0;
           if (hasb) mask[(size_t)yb * nx + n] = vb[q] > T(0) ? 1 : 0;
+          // t is zero off Ic and only written on it (DirPro): an element
+          // leaving Ic gets its zero here
+          if (pa[q] > T(0) && !(va[q] > T(0))) t[(size_t)ya * nx + n] = T(0);
+          if (hasb && pb[q] > T(0) && !(vb[q] > T(0))) t[(size_t)yb * nx + n] = T(0);
         }
       }
     }
@@ -550,12 +554,14 @@ struct DirPro {
   template <int NTHR>
   __device__ void commit(int ya, int yb, bool hasb, int nxl, const T (&va)[PER],
                          const T (&vb)[PER]) {
+    // only on Ic: off Ic t stays zero (the prepare kernel clears it, and
+    // UpdatePro zeroes each element that leaves Ic)
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int n = threadIdx.x + q * NTHR;
       if (n < nxl) {
-        t[(size_t)ya * nx + n] = va[q];
-        if (hasb) t[(size_t)yb * nx + n] = vb[q];
+        if (ca[q]) t[(size_t)ya * nx + n] = va[q];
+        if (hasb && cb[q]) t[(size_t)yb * nx + n] = vb[q];
       }
     }
   }
