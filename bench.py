@@ -103,10 +103,11 @@ def loop_bytes(f, w=4):
     """Algorithmic bytes per grid element of one CG iteration at contact
     fraction f, for w-byte reals (4 FP32, 8 FP64).  In FP32: update + R2C
     21 + 4 f (p, g, flags, spectrum; t on the contact set), column sweep 20,
-    C2R + gap 17, direction + R2C 13 + 8 f (flags, t, spectrum; g and t on
-    the contact set), column energy 12: 83 + 12 f.  The contact flags are 3
-    of those bytes and stay one byte per element in FP64."""
-    return (80.0 + 12.0 * f) * w / 4 + 3.0
+    C2R + gap 17, direction + R2C 9 + 12 f (flags, spectrum; g and t read
+    and t written on the contact set), column energy 12: 79 + 16 f.  The
+    contact flags are 3 of those bytes and stay one byte per element in
+    FP64."""
+    return (76.0 + 16.0 * f) * w / 4 + 3.0
 
 
 def timed(bem, K, h_dev, depths, precision, steps, warmup, torch, chains, clock=True):
@@ -672,9 +673,10 @@ def main():
     solves64 = N_DEPTHS * args.fp64_steps / t64
     ms_step = t32 / args.steps * 1e3
     # whole-loop effective bandwidth: algorithmic bytes per element per CG
-    # iteration (five launches) 83 + 12 f in FP32, with f the contact
-    # fraction (the direction and update prologues read t and g only in the
-    # contact set), 163 + 24 f in FP64; f of each solve's final contact set
+    # iteration (five launches) 79 + 16 f in FP32, with f the contact
+    # fraction (the direction and update prologues read t and g, and the
+    # direction prologue writes t, only in the contact set), 155 + 32 f in
+    # FP64; f of each solve's final contact set
     loop32 = sum(loop_bytes(x["n_contact"] / (N * N)) * N * N * x["iters"]
                  for x in res32[-1]) / (t32 / args.steps) / 1e9
     loop64 = sum(loop_bytes(x["n_contact"] / (N * N), 8) * N * N * x["iters"]
