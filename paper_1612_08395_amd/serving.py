@@ -7,7 +7,8 @@ timing only; every solve runs in the library.
 
 runs the seeded request stream (inputs.serving_requests) at saturation for
 both precisions, then with Poisson arrivals at 0.8 x the FP64 saturation
-rate, and writes the statistics as JSON.
+rate, and writes the statistics as JSON; --phase curves runs each request's
+loading curve with and without server sessions instead.
 """
 import argparse
 import json
@@ -125,8 +126,9 @@ def main():
     ap.add_argument("--batch-slots", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=8.0)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--phase", choices=("all", "saturation", "poisson"), default="all",
-                    help="saturation runs, Poisson runs (needs --qps), or both")
+    ap.add_argument("--phase", choices=("all", "saturation", "poisson", "curves"), default="all",
+                    help="saturation runs, Poisson runs (needs --qps), both, or the loading "
+                         "curves of the requests with and without sessions")
     ap.add_argument("--continuous-k", action="store_true",
                     help="k off the 0.05 grid: every request builds its influence operator")
     ap.add_argument("--qps", type=float, default=None,
@@ -140,8 +142,16 @@ def main():
     out = {"requests": a.requests, "seed": a.seed, "continuous_k": a.continuous_k, "slots": a.slots,
            "batch_slots": a.batch_slots, "budget_bytes": budget}
     sat = {}
+    if a.phase == "curves":
+        for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
+            for sessions in (True, False):
+                key = f"{name}_curves_{'sessions' if sessions else 'independent'}"
+                out[key] = run_curves(reqs, prec, sessions, n_slots=a.slots,
+                                      budget_bytes=budget, batch_slots=a.batch_slots)
+                print(f"[serving] {key} {out[key]['solves_per_s']:.1f} solves/s", file=sys.stderr,
+                      flush=True)
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
-        if a.phase == "poisson":
+        if a.phase in ("poisson", "curves"):
             break
         s = run_stream(reqs, prec, None, a.slots, budget, batch_slots=a.batch_slots,
                        progress=500)
@@ -151,7 +161,7 @@ def main():
               flush=True)
     qps = a.qps if a.qps else 0.8 * sat.get("fp64", 0.0)
     for prec, name in ((bem.BEM_FP64, "fp64"), (bem.BEM_MIXED, "mixed")):
-        if a.phase == "saturation" or qps <= 0:
+        if a.phase in ("saturation", "curves") or qps <= 0:
             break
         s = run_stream(reqs, prec, qps, a.slots, budget, seed=7, batch_slots=a.batch_slots,
                        progress=500)
