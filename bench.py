@@ -508,7 +508,7 @@ def serving(count, slots, bem):
     own) and with continuous k (no influence operator reused) for
     comparison; and the requests the MIXED path stopped at its
     rounding floor (BEM_EFLOOR), solved alone in both precisions, with their
-    pressure difference; then loading curves of 40 of the requests with and
+    pressure difference; then the loading curves of the requests with and
     without server sessions (serving.run_curves)."""
     from paper_1612_08395_amd import inputs
     from paper_1612_08395_amd.serving import KEYS_POISSON, KEYS_SAT, run_stream
@@ -554,11 +554,11 @@ def serving(count, slots, bem):
                        "contact_mixed": c32, "contact_fp64": c64})
     out["mixed_floor_requests"] = floors
     # loading curves (8 steps each; adhesive requests 4 loading + 4 pull-off
-    # steps) of the first 40 requests, MIXED: one server session per curve
+    # steps) of the stream's requests, MIXED: one server session per curve
     # (state resident on the device, each step warm-started) against every
     # step an independent cold request
     from paper_1612_08395_amd.serving import run_curves
-    cur = reqs[:40]
+    cur = reqs
     out["curves_mixed"] = {"sessions": run_curves(cur, bem.BEM_MIXED, True, n_slots=slots),
                            "independent": run_curves(cur, bem.BEM_MIXED, False, n_slots=slots)}
     return out
